@@ -1,0 +1,425 @@
+"""Seeded synthetic graph inputs for the k-core decomposition path and its oracle.
+
+This module builds graphs only: it holds none of the decomposition's arithmetic.
+Both the HIP path (through the package's Python binding) and the CPU oracle read
+the CSR arrays it produces, so parity never depends on how a graph was drawn.
+
+Every random draw is the i-th output of a SplitMix64 stream (Steele, Lea and
+Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
+``z = seed + (i + 1) * 0x9E3779B97F4A7C15`` followed by the published
+three-step finaliser.  It is evaluated with int64 tensor arithmetic (which wraps
+modulo 2**64), so a graph is bit-identical on the CPU and on a GPU and for any
+thread count.
+
+Graph model (the paper's storage, Section II-B "Graph Storage"): an undirected
+simple graph stored as CSR with both directions of every edge, rows sorted,
+no self-loops and no duplicate entries.  ``m`` is the number of directed
+entries, the |E| convention of the paper's dataset table (d_avg = |E|/|V|).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+__all__ = [
+    "CSRGraph", "csr_from_pairs", "rand64", "uniform_u32", "stream_seed",
+    "er_gnp", "er_gnm", "rmat", "plant_block", "permute_pow2",
+    "g1", "complete", "cycle", "path", "star", "complete_bipartite",
+    "hypercube", "circulant", "disjoint_union", "empty_graph", "from_edge_list",
+    "er_10k", "rmat22", "rmat26_block", "fingerprint",
+]
+
+_MASK64 = (1 << 64) - 1
+
+
+def _s64(x: int) -> int:
+    """Reinterpret an unsigned 64-bit Python int as a signed int64 value."""
+    x &= _MASK64
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+_GOLD = _s64(0x9E3779B97F4A7C15)
+_MIX1 = _s64(0xBF58476D1CE4E5B9)
+_MIX2 = _s64(0x94D049BB133111EB)
+
+
+def _lsr(x: torch.Tensor, s: int) -> torch.Tensor:
+    """Logical right shift of int64 values (torch's >> is arithmetic)."""
+    return (x >> s) & ((1 << (64 - s)) - 1)
+
+
+def _mix(z: torch.Tensor) -> torch.Tensor:
+    z = (z ^ _lsr(z, 30)) * _MIX1
+    z = (z ^ _lsr(z, 27)) * _MIX2
+    return z ^ _lsr(z, 31)
+
+
+def _mix_int(z: int) -> int:
+    z &= _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def stream_seed(*keys: int) -> int:
+    """Derive an independent 64-bit stream seed from integer keys (host side)."""
+    s = 0x5DEECE66D
+    for k in keys:
+        s = _mix_int(s + (int(k) + 1) * 0x9E3779B97F4A7C15)
+    return _s64(s)
+
+
+def rand64(seed: int, idx: torch.Tensor) -> torch.Tensor:
+    """Output number ``idx`` of the SplitMix64 stream ``seed`` (int64 tensor)."""
+    return _mix(seed + (idx + 1) * _GOLD)
+
+
+def uniform_u32(seed: int, idx: torch.Tensor) -> torch.Tensor:
+    """Uniform integers in [0, 2**32) from the top half of ``rand64``."""
+    return _lsr(rand64(seed, idx), 32)
+
+
+@dataclass
+class CSRGraph:
+    """An undirected simple graph in CSR form (both directions stored)."""
+
+    name: str
+    n: int
+    m: int
+    offsets: torch.Tensor  # int32 or int64, shape [n + 1]
+    cols: torch.Tensor     # int32, shape [m]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def offsets_i64(self) -> bool:
+        return self.offsets.dtype == torch.int64
+
+    def to(self, device) -> "CSRGraph":
+        return CSRGraph(self.name, self.n, self.m, self.offsets.to(device),
+                        self.cols.to(device), dict(self.meta))
+
+    def with_offsets(self, dtype: torch.dtype) -> "CSRGraph":
+        if dtype == torch.int32 and self.m >= 2**31:
+            raise ValueError("int32 offsets cannot address m >= 2**31 entries")
+        return CSRGraph(self.name, self.n, self.m, self.offsets.to(dtype),
+                        self.cols, dict(self.meta))
+
+    def degrees(self) -> torch.Tensor:
+        o = self.offsets.to(torch.int64)
+        return o[1:] - o[:-1]
+
+    def edge_pairs(self):
+        """(src, dst) int64 tensors of all directed entries."""
+        deg = self.degrees()
+        src = torch.repeat_interleave(torch.arange(self.n, device=deg.device), deg)
+        return src, self.cols.to(torch.int64)
+
+
+def csr_from_pairs(n: int, src: torch.Tensor, dst: torch.Tensor, *,
+                   offsets_dtype: torch.dtype = torch.int32, name: str = "graph",
+                   meta: dict | None = None) -> CSRGraph:
+    """Symmetrise, drop self-loops and duplicates, and sort into CSR."""
+    src = src.to(torch.int64)
+    dst = dst.to(torch.int64)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    key = torch.cat([src * n + dst, dst * n + src])
+    del src, dst, keep
+    key = torch.unique(key)  # sorted ascending: row-major CSR order
+    rows = torch.div(key, n, rounding_mode="floor")
+    cols = (key - rows * n).to(torch.int32)
+    del key
+    counts = torch.bincount(rows, minlength=n)
+    del rows
+    m = int(cols.numel())
+    if offsets_dtype == torch.int32 and m >= 2**31:
+        raise ValueError("graph too large for int32 offsets")
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=cols.device)
+    offsets[1:] = torch.cumsum(counts, 0)
+    return CSRGraph(name, n, m, offsets.to(offsets_dtype), cols, meta or {})
+
+
+def from_edge_list(n: int, edges, *, name: str = "graph",
+                   offsets_dtype: torch.dtype = torch.int32) -> CSRGraph:
+    """CSR of an explicit undirected edge list [(u, v), ...]."""
+    if len(edges) == 0:
+        src = torch.zeros(0, dtype=torch.int64)
+        dst = torch.zeros(0, dtype=torch.int64)
+    else:
+        t = torch.tensor(edges, dtype=torch.int64)
+        src, dst = t[:, 0], t[:, 1]
+    return csr_from_pairs(n, src, dst, offsets_dtype=offsets_dtype, name=name)
+
+
+# ---------------------------------------------------------------------------
+# Small structured graphs (worked example and closed-form families)
+# ---------------------------------------------------------------------------
+
+def g1() -> CSRGraph:
+    """The paper's running example G1 (Fig. 1), with the edge list implied by
+    the text: v5 has degree 5 (its h-index starts at 5, Section II-C), v5's
+    neighbours hold degrees 1,1,2,2,3 (Fig. 6), and v3 and v5 are the two
+    vertices whose residual degree falls under their coreness (Section III-A).
+    """
+    edges = [(0, 5), (1, 5), (2, 5), (3, 5), (4, 5), (2, 3), (3, 4)]
+    return from_edge_list(6, edges, name="G1")
+
+
+def empty_graph(n: int) -> CSRGraph:
+    return from_edge_list(n, [], name=f"empty{n}")
+
+
+def complete(n: int) -> CSRGraph:
+    return from_edge_list(n, [(i, j) for i in range(n) for j in range(i + 1, n)],
+                          name=f"K{n}")
+
+
+def cycle(n: int) -> CSRGraph:
+    return from_edge_list(n, [(i, (i + 1) % n) for i in range(n)], name=f"C{n}")
+
+
+def path(n: int) -> CSRGraph:
+    i = torch.arange(max(n - 1, 0), dtype=torch.int64)
+    return csr_from_pairs(n, i, i + 1, name=f"P{n}")
+
+
+def star(leaves: int) -> CSRGraph:
+    i = torch.arange(1, leaves + 1, dtype=torch.int64)
+    return csr_from_pairs(leaves + 1, torch.zeros_like(i), i, name=f"star{leaves}")
+
+
+def complete_bipartite(a: int, b: int) -> CSRGraph:
+    u = torch.arange(a, dtype=torch.int64).repeat_interleave(b)
+    v = a + torch.arange(b, dtype=torch.int64).repeat(a)
+    return csr_from_pairs(a + b, u, v, name=f"K{a},{b}")
+
+
+def hypercube(d: int) -> CSRGraph:
+    n = 1 << d
+    v = torch.arange(n, dtype=torch.int64)
+    src = torch.cat([v for _ in range(d)]) if d else v[:0]
+    dst = torch.cat([v ^ (1 << b) for b in range(d)]) if d else v[:0]
+    return csr_from_pairs(n, src, dst, name=f"Q{d}")
+
+
+def circulant(n: int, jumps) -> CSRGraph:
+    v = torch.arange(n, dtype=torch.int64)
+    src = torch.cat([v for _ in jumps])
+    dst = torch.cat([(v + j) % n for j in jumps])
+    return csr_from_pairs(n, src, dst, name=f"circ{n}{list(jumps)}")
+
+
+def disjoint_union(*graphs: CSRGraph) -> CSRGraph:
+    srcs, dsts, base = [], [], 0
+    for g in graphs:
+        s, d = g.edge_pairs()
+        srcs.append(s + base)
+        dsts.append(d + base)
+        base += g.n
+    return csr_from_pairs(base, torch.cat(srcs), torch.cat(dsts),
+                          name="+".join(g.name for g in graphs))
+
+
+# ---------------------------------------------------------------------------
+# Random graph models
+# ---------------------------------------------------------------------------
+
+def er_gnp(n: int, avg_deg: float, seed: int, *, device="cpu",
+           offsets_dtype=torch.int32, row_chunk: int = 512) -> CSRGraph:
+    """Exact Erdos-Renyi G(n, p) with p = avg_deg / (n - 1): every pair i < j
+    is kept iff its 32-bit draw is below round(p * 2**32).  O(n**2) draws, so
+    meant for n up to a few tens of thousands."""
+    p = avg_deg / max(n - 1, 1)
+    thresh = int(round(p * 2**32))
+    s = stream_seed(seed, 0xE5)
+    srcs, dsts = [], []
+    j = torch.arange(n, dtype=torch.int64, device=device)
+    for i0 in range(0, n, row_chunk):
+        i = torch.arange(i0, min(n, i0 + row_chunk), dtype=torch.int64, device=device)
+        idx = i[:, None] * n + j[None, :]
+        keep = (j[None, :] > i[:, None]) & (uniform_u32(s, idx) < thresh)
+        ii, jj = torch.nonzero(keep, as_tuple=True)
+        srcs.append(i[ii])
+        dsts.append(jj)
+    return csr_from_pairs(n, torch.cat(srcs), torch.cat(dsts), offsets_dtype=offsets_dtype,
+                          name=f"ER-gnp(n={n},d={avg_deg},seed={seed})",
+                          meta={"model": "gnp", "p_u32": thresh, "seed": seed})
+
+
+def er_gnm(n: int, avg_deg: float, seed: int, *, device="cpu",
+           offsets_dtype=torch.int32) -> CSRGraph:
+    """Erdos-Renyi by M = round(avg_deg * n / 2) uniform endpoint pairs drawn
+    with replacement; self-loops and repeats are then dropped (a G(n, M)
+    approximation of G(n, p) for sizes where O(n**2) draws are too many)."""
+    M = int(round(avg_deg * n / 2))
+    s = stream_seed(seed, 0xE6)
+    e = torch.arange(M, dtype=torch.int64, device=device)
+    src = _lsr(rand64(s, 2 * e), 1) % n
+    dst = _lsr(rand64(s, 2 * e + 1), 1) % n
+    return csr_from_pairs(n, src, dst, offsets_dtype=offsets_dtype,
+                          name=f"ER-gnm(n={n},d={avg_deg},seed={seed})",
+                          meta={"model": "gnm", "M": M, "seed": seed})
+
+
+def permute_pow2(x: torch.Tensor, bits: int, seed: int) -> torch.Tensor:
+    """A seeded bijection of [0, 2**bits): three rounds of (multiply by an odd
+    constant, xorshift, add) modulo 2**bits; each step is invertible."""
+    if bits == 0:
+        return x
+    mask = (1 << bits) - 1
+    sh = (bits + 1) // 2
+    for r in range(3):
+        odd = (stream_seed(seed, r, 1) | 1) & mask | 1
+        add = stream_seed(seed, r, 2) & mask
+        x = (x * odd) & mask
+        x = x ^ (x >> sh)
+        x = (x + add) & mask
+    return x
+
+
+def _permute_n(x: torch.Tensor, n: int, seed: int) -> torch.Tensor:
+    """Bijection of [0, n) by cycle-walking ``permute_pow2`` on the next power of 2."""
+    bits = max(1, (n - 1).bit_length())
+    y = permute_pow2(x, bits, seed)
+    for _ in range(1 << 12):
+        bad = y >= n
+        if not bool(bad.any()):
+            return y
+        y = torch.where(bad, permute_pow2(y, bits, seed), y)
+    raise RuntimeError("cycle walk did not converge")
+
+
+def _rmat_endpoints(e: torch.Tensor, scale: int, seed: int, thr) -> tuple:
+    """Graph500-style recursive quadrant descent for edge ids ``e`` (no noise)."""
+    A, AB, ABC = thr
+    src = torch.zeros_like(e)
+    dst = torch.zeros_like(e)
+    h = None
+    for lvl in range(scale):
+        if lvl % 2 == 0:
+            h = rand64(seed, e * 32 + lvl // 2)
+            r = _lsr(h, 32)
+        else:
+            r = h & 0xFFFFFFFF
+        q = (r >= A).to(torch.int64) + (r >= AB).to(torch.int64) + (r >= ABC).to(torch.int64)
+        src = (src << 1) | (q >> 1)
+        dst = (dst << 1) | (q & 1)
+    return src, dst
+
+
+def rmat(scale: int, edge_factor: int, seed: int, *, a=0.57, b=0.19, c=0.19,
+         n: int | None = None, permute: bool = True, device="cpu",
+         offsets_dtype=torch.int32, chunk: int = 1 << 25,
+         extra_pairs=None, name: str | None = None) -> CSRGraph:
+    """R-MAT graph: ``edge_factor * n`` generated edges over n = 2**scale
+    vertices (or a given n <= 2**scale, endpoints >= n redrawn), quadrant
+    probabilities (a, b, c, 1-a-b-c) quantised to 1/2**32, then a seeded
+    vertex relabelling, symmetrisation, dedup and self-loop removal.
+    ``extra_pairs`` (src, dst) are appended before the CSR is built."""
+    if n is None:
+        n = 1 << scale
+    assert n <= (1 << scale)
+    thr = (int(round(a * 2**32)), int(round((a + b) * 2**32)), int(round((a + b + c) * 2**32)))
+    M = edge_factor * n
+    s = stream_seed(seed, 0x4D)
+    psd = stream_seed(seed, 0x50)
+    srcs, dsts = [], []
+    for e0 in range(0, M, chunk):
+        e = torch.arange(e0, min(M, e0 + chunk), dtype=torch.int64, device=device)
+        src, dst = _rmat_endpoints(e, scale, s, thr)
+        for attempt in range(1, 257):
+            bad = (src >= n) | (dst >= n)
+            if not bool(bad.any()):
+                break
+            rs, rd = _rmat_endpoints(e[bad] + attempt * (1 << 40), scale, s, thr)
+            src[bad], dst[bad] = rs, rd
+        else:
+            keep = (src < n) & (dst < n)
+            src, dst = src[keep], dst[keep]
+        if permute:
+            src = _permute_n(src, n, psd)
+            dst = _permute_n(dst, n, psd)
+        srcs.append(src)
+        dsts.append(dst)
+    if extra_pairs is not None:
+        srcs.append(extra_pairs[0].to(device))
+        dsts.append(extra_pairs[1].to(device))
+    src = torch.cat(srcs)
+    dst = torch.cat(dsts)
+    del srcs, dsts
+    return csr_from_pairs(n, src, dst, offsets_dtype=offsets_dtype,
+                          name=name or f"RMAT(scale={scale},ef={edge_factor},seed={seed})",
+                          meta={"model": "rmat", "scale": scale, "edge_factor": edge_factor,
+                                "abc": (a, b, c), "seed": seed})
+
+
+def plant_block(n: int, size: int, p: float, seed: int, *, device="cpu"):
+    """Pairs of a planted dense block: ``size`` distinct vertices of [0, n)
+    (a seeded bijection's images of 0..size-1), each of their pairs kept with
+    probability p.  Returns (src, dst, members)."""
+    members = _permute_n(torch.arange(size, dtype=torch.int64, device=device), n,
+                         stream_seed(seed, 0xB1))
+    thresh = int(round(p * 2**32))
+    s = stream_seed(seed, 0xB2)
+    i = torch.arange(size, dtype=torch.int64, device=device)
+    idx = i[:, None] * size + i[None, :]
+    keep = (i[None, :] > i[:, None]) & (uniform_u32(s, idx) < thresh)
+    ii, jj = torch.nonzero(keep, as_tuple=True)
+    return members[ii], members[jj], members
+
+
+def fingerprint(g: CSRGraph) -> str:
+    """A 64-bit checksum of the CSR (n, m and every (row, col) entry)."""
+    src, dst = g.edge_pairs()
+    h = rand64(0x1234567, src * 4294967296 + dst)
+    acc = int(h.sum().item()) & _MASK64 if g.m else 0
+    acc = _mix_int(acc ^ _mix_int(g.n) ^ (_mix_int(g.m) << 1))
+    return f"{g.n}:{g.m}:{acc:016x}"
+
+
+# ---------------------------------------------------------------------------
+# The named workloads
+# ---------------------------------------------------------------------------
+
+def er_10k(seed: int = 1, device="cpu") -> CSRGraph:
+    """G(n=10,000, avg degree 8), int32 CSR."""
+    g = er_gnp(10_000, 8.0, seed, device=device)
+    g.name = f"ER-10k(seed={seed})"
+    return g
+
+
+def rmat22(seed: int = 22, device="cpu") -> CSRGraph:
+    """R-MAT scale 22, edge factor 16, (0.57, 0.19, 0.19, 0.05), permuted, int32."""
+    return rmat(22, 16, seed, device=device, offsets_dtype=torch.int32,
+                name=f"RMAT-22(ef=16,seed={seed})")
+
+
+def rmat26_block(seed: int = 26, block_seed: int = 2601, device="cpu",
+                 block: int = 3000, p: float = 0.6) -> CSRGraph:
+    """R-MAT scale 26, edge factor 16, plus a planted block of 3,000 vertices
+    at pair probability 0.6; int64 offsets, int32 cols."""
+    n = 1 << 26
+    bs, bd, _ = plant_block(n, block, p, block_seed, device=device)
+    g = rmat(26, 16, seed, device=device, offsets_dtype=torch.int64,
+             extra_pairs=(bs, bd), name=f"RMAT-26+block(seed={seed},block_seed={block_seed})")
+    g.meta.update({"block": block, "block_p": p, "block_seed": block_seed})
+    return g
+
+
+def scaled_rmat_block(scale: int, seed: int, block: int, p: float, block_seed: int,
+                      device="cpu", offsets_dtype=torch.int32) -> CSRGraph:
+    """Smaller relative of the RMAT-26 + block workload (same recipe, smaller
+    scale and block), for parity tests the oracle finishes in seconds."""
+    n = 1 << scale
+    bs, bd, _ = plant_block(n, block, p, block_seed, device=device)
+    return rmat(scale, 16, seed, device=device, offsets_dtype=offsets_dtype,
+                extra_pairs=(bs, bd),
+                name=f"RMAT-{scale}+block{block}(seed={seed})")
+
+
+def log_uniform_int(seed: int, idx: torch.Tensor, lo: int, hi: int) -> torch.Tensor:
+    """Integers log-uniform on [lo, hi] (exp of a 32-bit uniform, float64)."""
+    u = uniform_u32(seed, idx).to(torch.float64) / 2**32
+    return torch.floor(torch.exp(math.log(lo) + u * (math.log(hi + 1) - math.log(lo)))).to(torch.int64).clamp(lo, hi)

@@ -1,0 +1,165 @@
+/*
+ * CPU oracle for k-core decomposition -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, single-threaded, obviously-correct reference routines that the tests,
+ * the smoke check and the benchmark's CPU-baseline leg use to judge the GPU
+ * library.  Nothing in the product path links, loads or calls this file, and
+ * it shares no code, header or table with the GPU library.
+ *
+ * Graph input everywhere: an undirected simple graph in CSR with both
+ * directions of every edge stored (paper, Section II-B "Graph Storage"),
+ * offsets int64[n+1], neighbour ids int32[m].
+ *
+ *  - oracle_bz:            coreness by the Batagelj-Zaversnik O(n+m) bucket
+ *                          peel (cited in the paper's related work, Section
+ *                          VI-A); it computes exactly the definition of
+ *                          Section I: core(v) = the largest k such that v lies
+ *                          in the k-core, the maximal subgraph of minimum
+ *                          degree >= k.
+ *  - oracle_hindex_jacobi: the Index2core paradigm (Section II-A, Alg. 2) run
+ *                          in synchronous rounds: x_0 = deg and
+ *                          x_{t+1}(v) = H({x_t(u) : u in nbr(v)}), where H is
+ *                          the h-index (largest h with at least h neighbours
+ *                          valued >= h).  H is computed by sorting the
+ *                          neighbour values, not by a histogram.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
+int oracle_bz(int64_t n, const int64_t *off, const int32_t *adj, int32_t *core)
+{
+    if (n < 0 || (n > 0 && (!off || !core))) return -1;
+    if (n == 0) return 0;
+
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t d = off[v + 1] - off[v];
+        if (d < 0) return -1;
+        if (d > maxdeg) maxdeg = d;
+    }
+    int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *vert = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *bin = (int64_t *)calloc((size_t)maxdeg + 2, sizeof(int64_t));
+    if (!deg || !pos || !vert || !bin) {
+        free(deg); free(pos); free(vert); free(bin);
+        return -2;
+    }
+
+    /* Bucket the vertices by degree: bin[d] = first slot of degree class d in
+     * vert[], vert[] = vertices in non-decreasing degree order, pos[v] = slot
+     * of v in vert[]. */
+    for (int64_t v = 0; v < n; ++v) {
+        deg[v] = (int32_t)(off[v + 1] - off[v]);
+        bin[deg[v]]++;
+    }
+    int64_t start = 0;
+    for (int64_t d = 0; d <= maxdeg; ++d) {
+        int64_t cnt = bin[d];
+        bin[d] = start;
+        start += cnt;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        pos[v] = bin[deg[v]];
+        vert[pos[v]] = (int32_t)v;
+        bin[deg[v]]++;
+    }
+    for (int64_t d = maxdeg; d >= 1; --d) bin[d] = bin[d - 1];
+    bin[0] = 0;
+
+    /* Peel in non-decreasing current-degree order.  When v is removed its
+     * current degree is its coreness; every neighbour still ranked above v
+     * loses one degree and moves to the front of its (lower) bucket. */
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t v = vert[i];
+        for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+            int32_t u = adj[e];
+            if (deg[u] > deg[v]) {
+                int32_t du = deg[u];
+                int64_t pu = pos[u];
+                int64_t pw = bin[du];
+                int32_t w = vert[pw];
+                if (u != w) {
+                    pos[u] = pw; vert[pu] = w;
+                    pos[w] = pu; vert[pw] = u;
+                }
+                bin[du]++;
+                deg[u]--;
+            }
+        }
+    }
+    memcpy(core, deg, sizeof(int32_t) * (size_t)n);
+    free(deg); free(pos); free(vert); free(bin);
+    return 0;
+}
+
+static int cmp_desc_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x < y) - (x > y);
+}
+
+/* h-index of a multiset: the largest h such that at least h of the values
+ * are >= h.  With the values sorted in descending order s[0] >= s[1] >= ...,
+ * that is the largest h with s[h-1] >= h. */
+static int32_t h_index_sorted(int32_t *vals, int64_t cnt)
+{
+    qsort(vals, (size_t)cnt, sizeof(int32_t), cmp_desc_i32);
+    int64_t h = 0;
+    while (h < cnt && vals[h] >= h + 1) ++h;
+    return (int32_t)h;
+}
+
+/*
+ * Synchronous h-index iteration from x_0 = deg.
+ *   max_rounds:      stop after this many rounds even if not converged
+ *   x_out:           int32[n], the values after the last round executed
+ *   changed_per_round: optional int64[max_rounds]; entry t-1 = number of
+ *                    vertices whose value changed in round t
+ *   changed_round_of: optional int32[n]; the last round in which v changed
+ *                    (0 if never)
+ * Returns the number of rounds in which at least one value changed (the
+ * convergence round count when it converged), -1 on bad arguments, -2 on
+ * allocation failure.
+ */
+int64_t oracle_hindex_jacobi(int64_t n, const int64_t *off, const int32_t *adj,
+                             int64_t max_rounds, int32_t *x_out,
+                             int64_t *changed_per_round, int32_t *changed_round_of)
+{
+    if (n < 0 || (n > 0 && (!off || !x_out)) || max_rounds < 0) return -1;
+    if (n == 0) return 0;
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t d = off[v + 1] - off[v];
+        if (d > maxdeg) maxdeg = d;
+    }
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *y = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+    if (!x || !y || !buf) { free(x); free(y); free(buf); return -2; }
+    for (int64_t v = 0; v < n; ++v) x[v] = (int32_t)(off[v + 1] - off[v]);
+    if (changed_round_of) memset(changed_round_of, 0, sizeof(int32_t) * (size_t)n);
+
+    int64_t rounds = 0;
+    for (int64_t t = 1; t <= max_rounds; ++t) {
+        int64_t changed = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            int64_t d = off[v + 1] - off[v];
+            for (int64_t j = 0; j < d; ++j) buf[j] = x[adj[off[v] + j]];
+            y[v] = h_index_sorted(buf, d);
+            if (y[v] != x[v]) {
+                ++changed;
+                if (changed_round_of) changed_round_of[v] = (int32_t)t;
+            }
+        }
+        if (changed == 0) break;
+        if (changed_per_round) changed_per_round[t - 1] = changed;
+        rounds = t;
+        int32_t *tmp = x; x = y; y = tmp;
+    }
+    memcpy(x_out, x, sizeof(int32_t) * (size_t)n);
+    free(x); free(y); free(buf);
+    return rounds;
+}

@@ -1,0 +1,265 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests touches a GPU.  The oracle is only trusted because it
+passes them: worked-example values printed in the paper (G1, Fig. 1 / Fig. 6 /
+the PeelOne narrative), brute force on every labelled graph with up to six
+vertices and on random graphs up to fourteen, closed forms of textbook
+families, and cross-checks between independent routines (bucket peel vs
+synchronous h-index iteration vs serial PeelOne vs serial HistoCore).
+"""
+import itertools
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+
+def _edges_of(g):
+    s, d = g.edge_pairs()
+    return [(int(a), int(b)) for a, b in zip(s.tolist(), d.tolist()) if a < b]
+
+
+# ---------------------------------------------------------------- worked example G1
+
+def test_g1_coreness_all_routines(golden_g1):
+    g = gg.g1()
+    want = [int(x) for x in golden_g1["coreness"]]
+    edges = [tuple(int(t) for t in e.split("-")) for e in golden_g1["edges"]]
+    assert sorted(edges) == sorted(_edges_of(g))
+    assert oracle.bz_coreness(g.offsets, g.cols).tolist() == want
+    assert oracle.brute_coreness(6, edges) == want
+    assert oracle.peelone_trace(g.offsets, g.cols)["core"] == want
+    assert oracle.histocore_trace(g.offsets, g.cols)["core"] == want
+    x, _, _ = oracle.hindex_jacobi(g.offsets, g.cols)
+    assert x.tolist() == want
+
+
+def test_g1_under_core_vertices(golden_g1):
+    """Removing the vertices of coreness <= 2 found by the scans of iterations 1
+    and 2 of the general parallel peel (v0, v1, then v2, v4) leaves v3 and v5
+    with residual degree 1 < coreness 2: the under-core set (Section III-A)."""
+    g = gg.g1()
+    core = oracle.bz_coreness(g.offsets, g.cols)
+    removed = {0, 1, 2, 4}
+    under = []
+    for v in range(6):
+        if v in removed:
+            continue
+        res_deg = sum(1 for u in g.cols[g.offsets[v]:g.offsets[v + 1]].tolist() if u not in removed)
+        if res_deg < core[v]:
+            under.append(v)
+    assert under == [int(x) for x in golden_g1["under_core"]]
+
+
+def test_g1_peelone_trace(golden_g1):
+    t = oracle.peelone_trace(gg.g1().offsets, gg.g1().cols)
+    lv = {L["k"]: L for L in t["levels"]}
+    assert lv[2]["scan"] == [int(x) for x in golden_g1["peelone_k2_scan"]]
+    assert sorted(lv[2]["dynamic"]) == [int(x) for x in golden_g1["peelone_k2_dynamic"]]
+    assert lv[1]["scan"] == [0, 1] and lv[1]["dynamic"] == []
+    # v5: 5 -> 4 -> 3 during level 1, 3 -> 2 by the assertion decrement at level 2
+    assert t["trajectory"][5] == [5, 4, 3, 2]
+    assert t["trajectory"][3] == [3, 2]
+    assert len(t["levels"]) == 2  # levels = k_max (Table V: l1 equals k_max)
+
+
+def test_g1_histocore_trace(golden_g1):
+    g = gg.g1()
+    t = oracle.histocore_trace(g.offsets, g.cols)
+    want = {int(a): int(b) for a, b in (p.split(":") for p in golden_g1["v5_histogram"])}
+    h5 = t["init_histo"][5]
+    assert {i: h5[i] for i in range(1, 6) if h5[i]} == want
+    assert t["frontiers"] == [[3, 5]]
+    assert t["iterations"] == 1
+    assert t["cnt_ok"]
+    x1, per_round, last = oracle.hindex_jacobi(g.offsets, g.cols, max_rounds=1)
+    a, b = (int(v) for v in golden_g1["v5_round1_change"])
+    assert g.degrees()[5].item() == a and x1[5] == b == int(golden_g1["v5_hindex_round1"][0])
+    # v0, v1, v2, v4 never change (Section II-C: they need no re-estimation)
+    _, per_round, last = oracle.hindex_jacobi(g.offsets, g.cols)
+    assert [v for v in range(6) if last[v] == 0] == [0, 1, 2, 4]
+    assert per_round == [2]
+
+
+# ---------------------------------------------------------------- brute force
+
+def _all_graphs(n):
+    pairs = list(itertools.combinations(range(n), 2))
+    for mask in range(1 << len(pairs)):
+        yield [p for i, p in enumerate(pairs) if mask >> i & 1]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 6])
+def test_bz_equals_brute_force_exhaustive(n):
+    for edges in _all_graphs(n):
+        g = gg.from_edge_list(n, edges)
+        got = oracle.bz_coreness(g.offsets, g.cols).tolist()
+        assert got == oracle.brute_coreness(n, edges), (n, edges)
+
+
+def test_bz_equals_brute_force_random():
+    rng = random.Random(14)
+    for trial in range(10000):
+        n = rng.randint(1, 14)
+        p = rng.random()
+        edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+        g = gg.from_edge_list(n, edges)
+        assert oracle.bz_coreness(g.offsets, g.cols).tolist() == oracle.brute_coreness(n, edges)
+
+
+# ---------------------------------------------------------------- closed forms
+
+def _core(g):
+    return oracle.bz_coreness(g.offsets, g.cols)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 40])
+def test_complete_graph(n):
+    assert (_core(gg.complete(n)) == n - 1).all()
+
+
+@pytest.mark.parametrize("n", [3, 4, 11, 1000])
+def test_cycle(n):
+    assert (_core(gg.cycle(n)) == 2).all()
+
+
+def test_path_star_tree():
+    assert (_core(gg.path(5000)) == 1).all()
+    assert (_core(gg.star(100000)) == 1).all()
+    rng = random.Random(3)
+    n = 3000
+    edges = [(v, rng.randrange(v)) for v in range(1, n)]  # random recursive tree
+    assert (_core(gg.from_edge_list(n, edges)) == 1).all()
+
+
+def test_isolated_and_empty():
+    assert _core(gg.empty_graph(0)).tolist() == []
+    assert (_core(gg.empty_graph(17)) == 0).all()
+    g = gg.from_edge_list(5, [(1, 3)])
+    assert _core(g).tolist() == [0, 1, 0, 1, 0]
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 9), (3, 5), (7, 7), (12, 30)])
+def test_complete_bipartite(a, b):
+    assert (_core(gg.complete_bipartite(a, b)) == min(a, b)).all()
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 5, 10])
+def test_hypercube_is_d(d):
+    assert (_core(gg.hypercube(d)) == d).all()
+
+
+def test_circulant_regular():
+    g = gg.circulant(101, [1, 2, 5, 13])  # connected 8-regular
+    assert (_core(g) == 8).all()
+
+
+def test_disjoint_union_is_per_component():
+    parts = [gg.complete(9), gg.cycle(20), gg.star(7), gg.hypercube(4), gg.empty_graph(3)]
+    g = gg.disjoint_union(*parts)
+    want = np.concatenate([_core(p) for p in parts])
+    assert (_core(g) == want).all()
+    assert want[:9].tolist() == [8] * 9
+
+
+# ---------------------------------------------------------------- cross-checks
+
+def _random_graphs():
+    out = [gg.er_gnp(300, 6.0, s) for s in range(4)]
+    out += [gg.rmat(10, 8, s) for s in range(4)]
+    out.append(gg.scaled_rmat_block(11, 5, 60, 0.5, 9))
+    out.append(gg.disjoint_union(gg.path(200), gg.complete(30), gg.star(50)))
+    return out
+
+
+@pytest.mark.parametrize("g", _random_graphs(), ids=lambda g: g.name)
+def test_independent_routines_agree(g):
+    """Bucket peel, h-index fixed point (Index2core reaches coreness), serial
+    PeelOne and serial HistoCore all give the same vector."""
+    core = _core(g)
+    x, per_round, last = oracle.hindex_jacobi(g.offsets, g.cols)
+    assert (x == core).all()
+    po = oracle.peelone_trace(g.offsets, g.cols)
+    assert po["core"] == core.tolist()
+    hc = oracle.histocore_trace(g.offsets, g.cols)
+    assert hc["core"] == core.tolist()
+    # Theorem 2: HistoCore's frontier of iteration t is exactly the set of
+    # vertices whose h-index changes in synchronous round t.
+    assert hc["iterations"] == len(per_round)
+    for t, fr in enumerate(hc["frontiers"], start=1):
+        assert len(fr) == per_round[t - 1]
+    for v in range(g.n):
+        rounds_v = [t for t, fr in enumerate(hc["frontiers"], start=1) if v in set(fr)]
+        assert (rounds_v[-1] if rounds_v else 0) == last[v]
+    assert hc["cnt_ok"]
+    # PeelOne: level k peels exactly {v : core(v) = k}, each vertex once, and
+    # the level count is k_max (Table V: l1 equals k_max).
+    seen = []
+    for L in po["levels"]:
+        got = sorted(L["scan"] + L["dynamic"])
+        assert got == sorted(np.nonzero(core == L["k"])[0].tolist())
+        seen += got
+    assert sorted(seen) == sorted(np.nonzero(core > 0)[0].tolist())
+    assert len(po["levels"]) == int(core.max(initial=0))
+    # Corollary 1: no value ever drops below the level at which it is peeled.
+    for v in range(g.n):
+        assert min(po["trajectory"][v]) >= core[v]
+
+
+def test_hindex_rounds_monotone():
+    g = gg.rmat(11, 8, 1)
+    prev = g.degrees().numpy()
+    _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
+    for t in range(1, len(per_round) + 1):
+        x, _, _ = oracle.hindex_jacobi(g.offsets, g.cols, max_rounds=t)
+        assert (x <= prev).all() and int((x != prev).sum()) == per_round[t - 1]
+        prev = x
+
+
+def test_invariants_on_er10k():
+    g = gg.er_10k()
+    core = _core(g)
+    deg = g.degrees().numpy()
+    off = g.offsets.numpy().astype(np.int64)
+    cols = g.cols.numpy()
+    assert (core <= deg).all()
+    src = np.repeat(np.arange(g.n), deg)
+    # min degree >= k inside {core >= k}
+    for k in range(1, int(core.max()) + 1):
+        inside = core >= k
+        d_in = np.bincount(src[inside[src] & inside[cols]], minlength=g.n)
+        assert (d_in[inside] >= k).all()
+    # fixed point of the h-index operator
+    for v in range(g.n):
+        vals = np.sort(core[cols[off[v]:off[v + 1]]])[::-1]
+        h = 0
+        while h < len(vals) and vals[h] >= h + 1:
+            h += 1
+        assert h == core[v]
+    assert int((deg == 0).sum()) == int((core == 0).sum())
+
+
+def test_planted_mistake_is_caught():
+    """A peel that forgets the 'only neighbours ranked above' guard (a plausible
+    slip) disagrees with brute force on some six-vertex graph."""
+    def bad_peel(n, edges):
+        nbr = [set() for _ in range(n)]
+        for u, v in edges:
+            nbr[u].add(v); nbr[v].add(u)
+        deg = [len(s) for s in nbr]
+        alive = set(range(n))
+        core = [0] * n
+        while alive:
+            v = min(alive, key=lambda x: (deg[x], x))
+            core[v] = deg[v]
+            alive.discard(v)
+            for u in nbr[v]:
+                if u in alive:
+                    deg[u] -= 1  # should not drop below deg[v]
+        return core
+    caught = any(bad_peel(6, e) != oracle.brute_coreness(6, e) for e in _all_graphs(6))
+    assert caught
