@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the k-core hot path on one MI355X.
+
+One step = one full decomposition of the graph by PeelOne (Alg. 4) and one by
+HistoCore (Alg. 6), both through the C ABI, inputs resident in HBM.  The
+metric is coreness GTEPS: directed CSR entries |E| processed per second,
+counting each of the two decompositions (2 |E| per step).  Prints one JSON
+line; details of the run go to stderr.
+
+The graph is generated on the GPU from a counter-based RNG before timing.
+``--gpus`` above 1 is refused: this build runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_graph(name: str, device: str):
+    import graphgen as gg
+    if name == "er10k":
+        return gg.er_10k(device=device), "ER G(n=10000, avg deg 8), seed 1, int32 CSR"
+    if name == "rmat22":
+        return gg.rmat22(device=device), ("RMAT scale 22, edge factor 16, (0.57,0.19,0.19,0.05), "
+                                          "symmetrised, deduplicated, permuted, int32 CSR, seed 22")
+    if name == "rmat26":
+        return gg.rmat26_block(device=device), ("RMAT scale 26, edge factor 16 + planted block "
+                                                "3000 @ p=0.6, int64 offsets, seeds 26/2601")
+    raise SystemExit(f"unknown config {name}")
+
+
+def algorithmic_bytes(kind: str, st: dict, n: int, m: int, w: int) -> float:
+    """Bytes the method itself must move in one call, by kernel group.
+
+    drain (PeelOne scatter): per peeled vertex a queue read and two offsets,
+      per edge the column and core[u], per decrement an 8-byte atomic RMW, per
+      dynamic assertion a queue write and an output write.
+    update (HistoCore UpdateHisto): per changed vertex the queue entry, core,
+      oldcore and two offsets; per adjacency entry the column and core[u]; per
+      histogram move off[u] and two 8-byte atomic RMWs; per push a queue write.
+    sum (HistoCore SumHisto): per frontier vertex queue entry, core, offset and
+      three 4-byte writes, plus 4 bytes per bucket summed.
+    """
+    if kind == "drain":
+        P = st["frontier_total"]
+        return P * (4 + 2 * w) + 8 * m + 8 * st["atomics"] + 8 * st["pushes_dynamic"]
+    if kind == "update":
+        F = st["frontier_total"]
+        return (F * (12 + 2 * w) + 8 * st["edges_scanned"] + st["atomics"] * (w + 16)
+                + 4 * st["pushes_dynamic"])
+    if kind == "sum":
+        F = st["frontier_total"]
+        return F * (8 + w + 12) + 4 * st["buckets_scanned"]
+    raise ValueError(kind)
+
+
+GROUPS = {
+    "drain": ("peelone", ["po_scatter", "po_heavy"]),
+    "update": ("histocore", ["hc_update", "hc_update_heavy"]),
+    "sum": ("histocore", ["hc_sum", "hc_sum_heavy"]),
+}
+
+
+def cpu_baseline(g, budget_s: float):
+    import numpy as np
+    import oracle
+    off = g.offsets.cpu().numpy().astype(np.int64)
+    cols = g.cols.cpu().numpy()
+    runs, t_total, core = 0, 0.0, None
+    while runs < 1 or (t_total < budget_s and runs < 5):
+        t0 = time.perf_counter()
+        core = oracle.bz_coreness(off, cols)
+        t_total += time.perf_counter() - t0
+        runs += 1
+    return core, runs, t_total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="rmat22", choices=["er10k", "rmat22", "rmat26"])
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not bracket kernels with HIP events during the timed steps")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2402_15253_amd as pico
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g, desc = make_graph(args.config, dev)
+    torch.cuda.synchronize()
+    log(f"graph {g.name}: n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f}s")
+    n, m = g.n, g.m
+    w = 8 if g.offsets.dtype == torch.int64 else 4
+    algos = {"peelone": pico.algo_code("peelone", g.offsets),
+             "histocore": pico.algo_code("histocore", g.offsets)}
+    ws_bytes = max(pico.pico_workspace_bytes(n, m, a) for a in algos.values())
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    outs = {k: torch.empty(n, dtype=torch.int32, device=dev) for k in algos}
+    stream = torch.cuda.current_stream()
+    stats = {k: pico.PicoStats() for k in algos}
+
+    def step():
+        for name, a in algos.items():
+            rc = pico.pico_coreness_ws(g.offsets, g.cols, n, m, a, outs[name], ws, ws_bytes,
+                                       stats[name], stream)
+            if rc != pico.PICO_OK:
+                raise pico.PicoError(rc, pico.pico_last_error())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    pico.pico_profile_enable(not args.no_profile)
+    per_algo_ms = {k: 0.0 for k in algos}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        for k in algos:
+            per_algo_ms[k] += stats[k].elapsed_ms
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = pico.pico_profile_read() if not args.no_profile else {}
+    pico.pico_profile_enable(False)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = 2 * m * args.steps / elapsed / 1e9
+
+    st = {k: stats[k].as_dict() for k in algos}
+    log(json.dumps({"stats": st}))
+    log("kernel times over the timed steps (launches, total ms):")
+    for name, (cnt, tot) in sorted(prof.items(), key=lambda x: -x[1][1]):
+        log(f"  {name:18s} {cnt:8d} {tot:10.3f}")
+
+    # Roofline of the kernel group that takes the most time.
+    roofline = None
+    if prof:
+        best = None
+        for grp, (algo, kernels) in GROUPS.items():
+            t = sum(prof.get(kn, (0, 0.0))[1] for kn in kernels)
+            launches = sum(prof.get(kn, (0, 0.0))[0] for kn in kernels)
+            if launches and (best is None or t > best[1]):
+                best = (grp, t, launches, algo, kernels)
+        grp, t_ms, launches, algo, kernels = best
+        bytes_per_call = algorithmic_bytes(grp, st[algo], n, m, w)
+        achieved = bytes_per_call * args.steps / (t_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "+".join(kernels), "launches_per_step": launches / args.steps,
+                    "avg_launch_us": round(t_ms / launches * 1e3, 2),
+                    "algorithmic_bytes_per_step": int(bytes_per_call)}
+
+    # Parity against the oracle (and the CPU baseline timing of the same oracle).
+    want = None
+    cpu = None
+    if args.cpu_budget > 0:
+        want, runs, t_cpu = cpu_baseline(g, args.cpu_budget)
+        cpu = {"value": round(m * runs / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle",
+               "sample": f"Batagelj-Zaversnik peel, single thread, whole {args.config} graph, "
+                         f"{runs} run(s), {t_cpu:.1f}s; host {platform.processor() or 'x86_64'} "
+                         f"nproc={os.cpu_count()}"}
+    else:
+        import oracle
+        want = oracle.bz_coreness(g.offsets, g.cols)
+    parity = {k: bool(np.array_equal(outs[k].cpu().numpy(), want)) for k in algos}
+    if not all(parity.values()):
+        log(f"PARITY FAILURE: {parity}")
+
+    rec = {
+        "metric": "coreness GTEPS (|E|/s) + %HBM peak",
+        "value": round(value, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "m": m, "step": "PeelOne + HistoCore, one each",
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_algo_ms": {k: round(v / args.steps, 3) for k, v in per_algo_ms.items()},
+        "per_algo_gteps": {k: round(m / (v / args.steps / 1e3) / 1e9, 3)
+                           for k, v in per_algo_ms.items()},
+        "levels_l1": st["peelone"]["iterations"], "rounds_l2": st["histocore"]["iterations"],
+        "k_max": int(want.max()) if want is not None and want.size else 0,
+        "parity": "bit-exact" if all(parity.values()) else parity,
+    }
+    print(json.dumps(rec), flush=True)
+    if not all(parity.values()):
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,363 @@
+// C ABI of the k-core library: argument checks, workspace, dispatch on the
+// offsets width, status codes and error strings.  The problem solved is the
+// one of the paper's Section I (coreness of every vertex of an undirected
+// graph); the algorithms live in peelone.hip (Alg. 4) and histocore.hip
+// (Alg. 6).
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pico {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+void *host_scratch(size_t bytes) {
+    static thread_local void *buf = nullptr;
+    static thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        size_t want = bytes < 4096 ? 4096 : bytes;
+        hipError_t e = hipHostMalloc(&buf, want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_error("hipHostMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+            buf = nullptr;
+            return nullptr;
+        }
+        cap = want;
+    }
+    return buf;
+}
+
+namespace {
+
+struct ProfRec {
+    const char *name;
+    hipEvent_t start, stop;
+};
+
+struct ProfState {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<ProfRec> pending;
+    std::vector<pico_kernel_stat> table;
+};
+
+thread_local ProfState g_prof;
+
+hipEvent_t prof_event() {
+    if (g_prof.used == g_prof.pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_prof.pool.push_back(e);
+    }
+    return g_prof.pool[g_prof.used++];
+}
+
+// Fold the recorded launches of the finished call into the table.
+int prof_resolve() {
+    int rc = PICO_OK;
+    for (const ProfRec &r : g_prof.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) != hipSuccess ||
+            hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+            set_error("profiling events could not be resolved");
+            rc = PICO_EHIP;
+            continue;
+        }
+        pico_kernel_stat *slot = nullptr;
+        for (auto &t : g_prof.table)
+            if (strcmp(t.name, r.name) == 0) slot = &t;
+        if (!slot) {
+            g_prof.table.push_back(pico_kernel_stat{r.name, 0, 0.0});
+            slot = &g_prof.table.back();
+        }
+        slot->launches += 1;
+        slot->total_ms += ms;
+    }
+    g_prof.pending.clear();
+    g_prof.used = 0;
+    return rc;
+}
+
+int check_device() {
+    int dev = -1;
+    PICO_HIP_TRY(hipGetDevice(&dev));
+    static int checked[64] = {0};  // 0 unknown, 1 ok, -1 unsupported
+    if (dev >= 0 && dev < 64 && checked[dev] != 0) return checked[dev] > 0 ? PICO_OK : PICO_ENOTSUP;
+    hipDeviceProp_t prop;
+    PICO_HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev >= 0 && dev < 64) checked[dev] = ok ? 1 : -1;
+    if (!ok) {
+        set_error("device %d is %s; this library is built for gfx950 only", dev, prop.gcnArchName);
+        return PICO_ENOTSUP;
+    }
+    return PICO_OK;
+}
+
+int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo,
+               const int32_t *out) {
+    int a = algo & PICO_ALGO_MASK;
+    if (a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) {
+        set_error("unknown algo %d", algo);
+        return PICO_EINVAL;
+    }
+    if ((algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64)) != 0) {
+        set_error("unknown flag bits in algo 0x%x", algo);
+        return PICO_EINVAL;
+    }
+    if (n < 0 || m < 0) {
+        set_error("negative size (n=%lld, m=%lld)", (long long)n, (long long)m);
+        return PICO_EINVAL;
+    }
+    if (n >= (int64_t)1 << 31) {
+        set_error("n=%lld does not fit 32-bit vertex ids", (long long)n);
+        return PICO_EINVAL;
+    }
+    if (!(algo & PICO_OFFSETS_I64) && m >= (int64_t)1 << 31) {
+        set_error("m=%lld needs int64 offsets (PICO_OFFSETS_I64)", (long long)m);
+        return PICO_EINVAL;
+    }
+    if (n > 0 && (!off || !out)) {
+        set_error("NULL offsets or output with n=%lld", (long long)n);
+        return PICO_EINVAL;
+    }
+    if (m > 0 && !cols) {
+        set_error("NULL columns with m=%lld", (long long)m);
+        return PICO_EINVAL;
+    }
+    return PICO_OK;
+}
+
+size_t ws_bytes_for(int64_t n, int64_t m, int algo) {
+    return (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m)
+                                                         : histocore_ws_bytes(n, m);
+}
+
+int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo, int32_t *out,
+             void *ws, size_t ws_bytes, pico_stats *st, hipStream_t s) {
+    const bool i64 = (algo & PICO_OFFSETS_I64) != 0;
+    if ((algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE) {
+        return i64 ? run_peelone<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
+                                          ws_bytes, st, s)
+                   : run_peelone<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws,
+                                          ws_bytes, st, s);
+    }
+    return i64 ? run_histocore<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
+                                        ws_bytes, st, s)
+               : run_histocore<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws,
+                                        ws_bytes, st, s);
+}
+
+template <typename Off>
+__global__ void validate_kernel(const Off *__restrict__ off, const int32_t *__restrict__ cols,
+                                long long n, long long m, int *__restrict__ bad) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        long long a = (long long)off[v], b = (long long)off[v + 1];
+        if (v == 0 && a != 0) atomicOr(bad, 1);
+        if (v == n - 1 && b != m) atomicOr(bad, 2);
+        if (b < a || a < 0 || b > m) {
+            atomicOr(bad, 4);
+            continue;
+        }
+        for (long long e = a; e < b; ++e) {
+            int u = cols[e];
+            if (u < 0 || u >= n) atomicOr(bad, 8);
+            else if (u == v) atomicOr(bad, 16);
+        }
+    }
+}
+
+}  // namespace
+
+int prof_begin(const char *name, hipStream_t s) {
+    if (!g_prof.on) return -1;
+    ProfRec r{name, prof_event(), prof_event()};
+    if (!r.start || !r.stop) return -1;
+    if (hipEventRecord(r.start, s) != hipSuccess) return -1;
+    g_prof.pending.push_back(r);
+    return (int)g_prof.pending.size() - 1;
+}
+
+void prof_end(int rec, hipStream_t s) {
+    if (rec >= 0) (void)hipEventRecord(g_prof.pending[rec].stop, s);
+}
+
+}  // namespace pico
+
+using namespace pico;
+
+extern "C" {
+
+const char *pico_version(void) { return "pico-mi355x 0.1 (gfx950)"; }
+
+const char *pico_last_error(void) { return g_err; }
+
+const char *pico_status_string(int status) {
+    switch (status) {
+        case PICO_OK: return "ok";
+        case PICO_EINVAL: return "invalid argument";
+        case PICO_ENOMEM: return "out of memory or workspace too small";
+        case PICO_EHIP: return "HIP runtime error";
+        case PICO_ENOTSUP: return "unsupported device or option";
+        case PICO_EBADCSR: return "malformed CSR graph";
+        default: return "unknown status";
+    }
+}
+
+int pico_profile_enable(int on) {
+    clear_error();
+    g_prof.on = on != 0;
+    if (g_prof.on) g_prof.table.clear();
+    return PICO_OK;
+}
+
+int pico_profile_read(pico_kernel_stat *out, int cap, int *count) {
+    clear_error();
+    if (!count || (cap > 0 && !out) || cap < 0) {
+        set_error("bad profile_read arguments");
+        return PICO_EINVAL;
+    }
+    *count = (int)g_prof.table.size();
+    for (int i = 0; i < cap && i < (int)g_prof.table.size(); ++i) out[i] = g_prof.table[i];
+    return PICO_OK;
+}
+
+int pico_workspace_bytes(int64_t n, int64_t m, int algo, size_t *bytes) {
+    clear_error();
+    int rc = check_args((const void *)1, (const int32_t *)1, n, m, algo, (const int32_t *)1);
+    if (rc) return rc;
+    if (!bytes) {
+        set_error("NULL bytes pointer");
+        return PICO_EINVAL;
+    }
+    *bytes = ws_bytes_for(n, m, algo);
+    return PICO_OK;
+}
+
+int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
+                     int algo, int32_t *out_core, void *workspace, size_t ws_bytes,
+                     pico_stats *stats, void *stream) {
+    clear_error();
+    if (stats) memset(stats, 0, sizeof(*stats));
+    int rc = check_args(csr_offsets, csr_cols, n, m, algo, out_core);
+    if (rc) return rc;
+    if (n == 0) return PICO_OK;
+    rc = check_device();
+    if (rc) return rc;
+    size_t need = ws_bytes_for(n, m, algo);
+    if (ws_bytes < need || !workspace) {
+        set_error("workspace of %zu bytes given, %zu needed", ws_bytes, need);
+        return PICO_ENOMEM;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return PICO_EINVAL;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    rc = dispatch(csr_offsets, csr_cols, n, m, algo, out_core, workspace, ws_bytes, stats,
+                  static_cast<hipStream_t>(stream));
+    if (rc) {
+        g_prof.pending.clear();
+        g_prof.used = 0;
+        return rc;
+    }
+    PICO_HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    rc = prof_resolve();
+    if (rc) return rc;
+    if (stats) {
+        stats->elapsed_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return PICO_OK;
+}
+
+int pico_coreness(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,
+                  int32_t *out_core, void *stream) {
+    clear_error();
+    int rc = check_args(csr_offsets, csr_cols, n, m, algo, out_core);
+    if (rc) return rc;
+    if (n == 0) return PICO_OK;
+    rc = check_device();
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t need = ws_bytes_for(n, m, algo);
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, need, s);
+    if (e != hipSuccess) {
+        set_error("hipMallocAsync(%zu) failed: %s", need, hipGetErrorString(e));
+        return PICO_ENOMEM;
+    }
+    rc = dispatch(csr_offsets, csr_cols, n, m, algo, out_core, ws, need, nullptr, s);
+    hipError_t fe = hipFreeAsync(ws, s);
+    if (rc) {
+        g_prof.pending.clear();
+        g_prof.used = 0;
+        return rc;
+    }
+    if (fe != hipSuccess) {
+        set_error("hipFreeAsync failed: %s", hipGetErrorString(fe));
+        return PICO_EHIP;
+    }
+    PICO_HIP_TRY(hipStreamSynchronize(s));
+    return prof_resolve();
+}
+
+int pico_validate_csr(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
+                      int algo, void *stream) {
+    clear_error();
+    int rc = check_args(csr_offsets, csr_cols, n, m, algo, (const int32_t *)1);
+    if (rc) return rc;
+    if (n == 0) return m == 0 ? PICO_OK : PICO_EBADCSR;
+    rc = check_device();
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int *bad = nullptr;
+    PICO_HIP_TRY(hipMallocAsync((void **)&bad, sizeof(int), s));
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
+    if (e == hipSuccess) {
+        int grid = (int)((n + 255) / 256 > 4096 ? 4096 : (n + 255) / 256);
+        if (algo & PICO_OFFSETS_I64)
+            hipLaunchKernelGGL(validate_kernel<int64_t>, dim3(grid), dim3(256), 0, s,
+                               static_cast<const int64_t *>(csr_offsets), csr_cols, (long long)n,
+                               (long long)m, bad);
+        else
+            hipLaunchKernelGGL(validate_kernel<int32_t>, dim3(grid), dim3(256), 0, s,
+                               static_cast<const int32_t *>(csr_offsets), csr_cols, (long long)n,
+                               (long long)m, bad);
+        e = hipGetLastError();
+    }
+    int hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t fe = hipFreeAsync(bad, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || fe != hipSuccess) {
+        set_error("validation failed to run: %s", hipGetErrorString(e != hipSuccess ? e : fe));
+        return PICO_EHIP;
+    }
+    if (hbad) {
+        set_error("malformed CSR (flags 0x%x: 1 off[0]!=0, 2 off[n]!=m, 4 bad offsets, "
+                  "8 column out of range, 16 self-loop)", hbad);
+        return PICO_EBADCSR;
+    }
+    return PICO_OK;
+}
+
+}  // extern "C"

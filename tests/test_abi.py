@@ -1,0 +1,54 @@
+"""Host-side checks of the C ABI: the library builds, loads and exports every
+entry point that include/pico.h declares; argument checks that need no GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2402_15253_amd as pico
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "pico.h")) as f:
+        text = f.read()
+    return re.findall(r"PICO_API\s+[\w\s\*]+?\b(pico_\w+)\s*\(", text)
+
+
+def test_header_declares_the_python_names():
+    names = _declared()
+    assert set(names) == set(pico.EXPORTED_SYMBOLS)
+    for name in names:
+        assert callable(getattr(pico, name))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(pico.library_path())
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_and_status_without_gpu():
+    assert pico.pico_workspace_bytes(0, 0, pico.PICO_ALGO_PEELONE) >= 0
+    a = pico.pico_workspace_bytes(1000, 8000, pico.PICO_ALGO_PEELONE)
+    b = pico.pico_workspace_bytes(1000, 8000, pico.PICO_ALGO_HISTOCORE)
+    assert a >= 4 * 4000 and b >= 4 * 8000
+    with pytest.raises(pico.PicoError):
+        pico.pico_workspace_bytes(-1, 0, pico.PICO_ALGO_PEELONE)
+    with pytest.raises(pico.PicoError):
+        pico.pico_workspace_bytes(10, 2**31, pico.PICO_ALGO_PEELONE)  # needs int64 offsets
+    assert pico.pico_workspace_bytes(10, 2**31, pico.PICO_ALGO_PEELONE | pico.PICO_OFFSETS_I64) > 0
+    assert pico.pico_status_string(pico.PICO_EINVAL) == "invalid argument"
+    assert "gfx950" in pico.pico_version()
+
+
+def test_argument_errors_need_no_device():
+    # rejected before any device work
+    assert pico.pico_coreness(None, None, -5, 0, 0, None) == pico.PICO_EINVAL
+    assert pico.pico_coreness(None, None, 10, 0, 0, None) == pico.PICO_EINVAL
+    assert "NULL" in pico.pico_last_error()
+    assert pico.pico_coreness(None, None, 0, 0, 7, None) == pico.PICO_EINVAL
+    assert pico.pico_coreness(None, None, 0, 0, 0, None) == pico.PICO_OK  # n == 0: no-op
+    assert pico.pico_coreness_ws(None, None, 0, 0, 1, None, None, 0) == pico.PICO_OK
