@@ -87,6 +87,12 @@ typedef struct pico_stats {
     int64_t pushes_dynamic; /* PeelOne: vertices asserted by the scatter (the
                                dynamic frontier) rather than found by a scan;
                                HistoCore: frontier entries pushed by UpdateHisto */
+    double phase_ms[8];     /* device wall time by phase, barrier waits included.
+                               PeelOne: [0] initialisation, [1] level scans,
+                               [2] level drains.  HistoCore: [0] core = deg,
+                               [1] InitHisto, [2] SumHisto, [3] SumHisto of
+                               large values, [4] UpdateHisto, [5] UpdateHisto
+                               of long rows. */
 } pico_stats;
 
 /* Accumulated HIP-event timing of one kernel over profiled calls. */

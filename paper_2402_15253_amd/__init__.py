@@ -50,10 +50,12 @@ class PicoStats(ctypes.Structure):
                 ("k_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("elapsed_ms", ctypes.c_double), ("edges_scanned", ctypes.c_int64),
                 ("atomics", ctypes.c_int64), ("buckets_scanned", ctypes.c_int64),
-                ("pushes_dynamic", ctypes.c_int64)]
+                ("pushes_dynamic", ctypes.c_int64), ("phase_ms", ctypes.c_double * 8)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("reserved", "phase_ms")}
+        d["phase_ms"] = [round(x, 4) for x in self.phase_ms]
+        return d
 
 
 class KernelStat(ctypes.Structure):

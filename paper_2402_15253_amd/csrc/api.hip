@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -41,6 +42,42 @@ void *host_scratch(size_t bytes) {
         cap = want;
     }
     return buf;
+}
+
+int persistent_grid(const void *kernel, int block, int max_per_cu, int *blocks) {
+    int dev = 0;
+    PICO_HIP_TRY(hipGetDevice(&dev));
+    int cus = 0, coop = 0;
+    PICO_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    PICO_HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) {
+        set_error("device %d does not support cooperative launches", dev);
+        return PICO_ENOTSUP;
+    }
+    int per_cu = 0;
+    PICO_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
+    if (per_cu > max_per_cu) per_cu = max_per_cu;
+    if (per_cu < 1) {
+        set_error("persistent kernel does not fit on a compute unit");
+        return PICO_ENOTSUP;
+    }
+    *blocks = per_cu * cus;
+    return PICO_OK;
+}
+
+int tune_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    int x = atoi(v);
+    return x > 0 ? x : dflt;
+}
+
+unsigned long long wall_ticks(double seconds) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;  // 100 MHz, the usual constant clock
+    return (unsigned long long)(seconds * 1000.0 * (double)khz);
 }
 
 namespace {

@@ -59,6 +59,422 @@ __device__ __forceinline__ long long wave_sum64(long long x) {
     return x;
 }
 
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    const int lane = lane_id();
+    for (int o = 1; o < kWave; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_max_int(int x) {
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Index of the lane owning position t of a wave-wide concatenation whose
+// exclusive prefix sums are `pre` (non-decreasing across lanes, pre of lane 0
+// is 0): the last lane j with pre_j <= t.  Binary lifting over lanes.
+__device__ __forceinline__ int wave_owner(int pre, int t) {
+    int pos = 0;
+    for (int s = 64; s > 0; s >>= 1) {
+        int idx = pos + s - 1;
+        int pm = __shfl(pre, idx < kWave ? idx : kWave - 1);
+        if (idx < kWave && pm <= t) pos += s;
+    }
+    return pos - 1;
+}
+
+// Agent-scope atomics with explicit ordering (HIP's atomicAdd & co. are
+// relaxed at agent scope).
+template <typename T>
+__device__ __forceinline__ T ld_acq(T *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_rlx(T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_rlx(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_rel(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T fadd_rel(T *p, T v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ bool cas_acq_rel(T *p, T expected, T desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A counter alone on its cache lines, so hot counters do not share a line.
+struct alignas(128) Line {
+    unsigned long long v;
+    unsigned long long pad[15];
+};
+
+// Grid-wide state of a persistent cooperative kernel: a two-level barrier,
+// an error flag and cumulative counters.  At every barrier the releasing
+// block copies all counters into snap[generation & 1], so every block takes
+// control decisions from the same values even though fast blocks resume
+// updating the counters before slow ones have left the barrier.
+constexpr int kNumCtr = 8;
+constexpr int kBarGroups = 8;  // one arrival counter per XCD (blocks go round-robin)
+struct GridState {
+    Line group_arrivals[kBarGroups];
+    Line top_arrivals;
+    Line gen;
+    Line error;
+    Line ctr[kNumCtr];
+    unsigned long long snap[2][kNumCtr];
+};
+
+// Phase timing: block 0 stamps the wall clock at phase boundaries.
+constexpr int kNumPhases = 8;
+struct PhaseClock {
+    unsigned long long last;
+    __device__ void start() { last = wall_clock64(); }
+    __device__ void lap(unsigned long long *acc) {
+        unsigned long long now = wall_clock64();
+        *acc += now - last;
+        last = now;
+    }
+};
+
+// Bounded wait: every spin loop gives up after `limit` wall-clock ticks and
+// raises the grid error flag, so no input can leave waves spinning forever.
+struct Waiter {
+    unsigned long long t0, limit;
+    unsigned n;
+    __device__ explicit Waiter(unsigned long long lim) : t0(wall_clock64()), limit(lim), n(0) {}
+    // true when the wait must stop (time limit hit or error raised elsewhere)
+    __device__ bool stop(GridState *gs) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++n & 63u) != 0) return false;
+        if (ld_rlx(&gs->error.v) != 0) return true;
+        if (wall_clock64() - t0 > limit) {
+            st_rlx(&gs->error.v, 1ull);
+            return true;
+        }
+        return false;
+    }
+};
+
+struct NoRelease {
+    __device__ void operator()(GridState *) const {}
+};
+
+__device__ __forceinline__ void fence_release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+__device__ __forceinline__ void fence_acquire() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Grid barrier for a cooperative grid (all blocks co-resident).  Two levels:
+// blocks arrive on the counter of their group (blockIdx % kBarGroups, i.e.
+// their XCD), the last of each group on the top counter, so no counter sees
+// more than about nblocks / 8 serialised atomics.  Counters only grow: the
+// b-th barrier completes when a counter reaches (b + 1) times its group
+// size, so nothing is ever reset.  Waiting blocks poll the generation word
+// with relaxed loads and fence once on the way out.
+//
+// `bar_no` counts the barriers this block has passed (the same sequence in
+// every block).  `on_release(gs)` runs on the releasing block after all have
+// arrived and before any is let go.  snap_out (LDS, kNumCtr + 1 entries)
+// receives the counters as they stood then, and the error flag.  Returns
+// false if the grid is in error.
+template <typename Rel = NoRelease>
+__device__ __forceinline__ bool grid_sync(GridState *gs, unsigned nblocks, unsigned long long limit,
+                                          unsigned long long *snap_out, unsigned long long &bar_no,
+                                          Rel on_release = Rel()) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned ngroups = nblocks < (unsigned)kBarGroups ? nblocks : (unsigned)kBarGroups;
+        const unsigned grp = blockIdx.x % ngroups;
+        const unsigned gsize = nblocks / ngroups + (grp < nblocks % ngroups ? 1u : 0u);
+        const unsigned long long b = bar_no;
+        fence_release();
+        unsigned long long a =
+            __hip_atomic_fetch_add(&gs->group_arrivals[grp].v, 1ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) + 1;
+        bool released = false;
+        if (a == (b + 1) * gsize) {
+            fence_acquire();
+            fence_release();
+            unsigned long long t =
+                __hip_atomic_fetch_add(&gs->top_arrivals.v, 1ull, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT) + 1;
+            if (t == (b + 1) * ngroups) {
+                fence_acquire();
+                on_release(gs);
+                for (int i = 0; i < kNumCtr; ++i) {
+                    unsigned long long c = ld_rlx(&gs->ctr[i].v);
+                    st_rlx(&gs->snap[b & 1][i], c);
+                    snap_out[i] = c;
+                }
+                fence_release();
+                st_rlx(&gs->gen.v, b + 1);
+                released = true;
+            }
+        }
+        if (!released) {
+            Waiter w(limit);
+            while (ld_rlx(&gs->gen.v) < b + 1) {
+                if (w.stop(gs)) break;
+            }
+            fence_acquire();
+            for (int i = 0; i < kNumCtr; ++i) snap_out[i] = ld_rlx(&gs->snap[b & 1][i]);
+        }
+        snap_out[kNumCtr] = ld_rlx(&gs->error.v);
+    }
+    ++bar_no;
+    __syncthreads();
+    return snap_out[kNumCtr] == 0;
+}
+
+// Block-wide exclusive scan of one int per thread; `lds` holds
+// kWavesPerBlock ints.  Returns the thread's prefix; `total` = block sum.
+__device__ __forceinline__ int block_excl_scan(int x, int &total, int *lds) {
+    const int w = threadIdx.x >> 6;
+    int incl = wave_incl_scan(x);
+    if (lane_id() == kWave - 1) lds[w] = incl;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+        int s = lds[i];
+        before += i < w ? s : 0;
+        total += s;
+    }
+    __syncthreads();
+    return before + incl - x;
+}
+
+// Largest index o in [0, kBlock) with pre[o] <= t, for a non-decreasing LDS
+// array pre with pre[0] = 0 (the item owning position t of a concatenation).
+__device__ __forceinline__ int block_owner(const int *pre, int t) {
+    int lo = 0;
+#pragma unroll
+    for (int s = kBlock / 2; s > 0; s >>= 1)
+        if (pre[lo + s] <= t) lo += s;
+    return lo;
+}
+
+// LDS staging of one workgroup-wide row expansion.
+struct ExpandLds {
+    int pre[kBlock];
+    long long e0[kBlock];
+    int p0[kBlock];
+    int p1[kBlock];
+    int scan[kWavesPerBlock];
+    long long scan_l[kWavesPerBlock];
+};
+
+// Workgroup-wide load-balanced expansion of up to kBlock adjacency rows, one
+// per thread (length d, first entry e0, two ints of payload): a prefix sum of
+// the lengths, then every thread takes R edges per step, each located by a
+// binary search over the prefix sums.  f(act[R], u[R], owner[R]) is called
+// by all threads together for each step; owner indexes the LDS payload.
+template <int R, typename F>
+__device__ __forceinline__ void block_expand(int d, long long e0, int p0, int p1,
+                                             const int32_t *__restrict__ cols, ExpandLds &L, F &&f) {
+    int total = 0;
+    int pre = block_excl_scan(d, total, L.scan);
+    L.pre[threadIdx.x] = pre;
+    L.e0[threadIdx.x] = e0;
+    L.p0[threadIdx.x] = p0;
+    L.p1[threadIdx.x] = p1;
+    __syncthreads();
+    for (int t0 = 0; t0 < total; t0 += kBlock * R) {
+        bool act[R];
+        int u[R], own[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int t = t0 + r * kBlock + (int)threadIdx.x;
+            act[r] = t < total;
+            int o = block_owner(L.pre, act[r] ? t : total - 1);
+            own[r] = o;
+            u[r] = act[r] ? cols[L.e0[o] + (t - L.pre[o])] : 0;
+        }
+        f(act, u, own);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Edge-balanced rounds.  A frontier list holds, per entry i, a vertex id, the
+// entry's start es[i] in the concatenation of the entries' adjacency rows
+// (non-decreasing in i) and the row's first CSR position rs[i].  A round
+// gives every workgroup an equal contiguous slice of the concatenated edges,
+// whatever the row lengths; each step loads the entries covering the next
+// kBlock * R edges into LDS and locates every edge's entry by binary search.
+
+constexpr int kEbR = 4;                   // edges per thread per step
+constexpr int kEbWin = kBlock * kEbR;     // edges per step
+struct EbLds {
+    int id[kEbWin + 1];
+    long long es[kEbWin + 1];
+    long long rs[kEbWin + 1];
+    int p0[kEbWin + 1];
+    int p1[kEbWin + 1];
+    long long next;
+};
+
+// Largest j in [0, w) with es[j] <= x (es non-decreasing, es[0] <= x).
+__device__ __forceinline__ int lds_owner(const long long *es, int w, long long x) {
+    int lo = 0, hi = w;  // invariant: es[lo] <= x, answer in [lo, hi)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (es[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Process edges [e_lo, e_hi) of the concatenation of entries [q0, q1), this
+// workgroup's share being an equal slice.  P0/P1 (may be null) are per-entry
+// payloads copied to LDS.  f(act[kEbR], u[kEbR], own[kEbR], L) is called by
+// all threads together for each step; own indexes L's entry arrays.
+template <typename F>
+__device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
+                                              const long long *__restrict__ es,
+                                              const long long *__restrict__ rs,
+                                              const int32_t *__restrict__ P0,
+                                              const int32_t *__restrict__ P1, long long q0, long long q1,
+                                              long long e_lo, long long e_hi,
+                                              const int32_t *__restrict__ cols, EbLds &L, F &&f) {
+    const long long span = e_hi - e_lo;
+    const long long lo = e_lo + span * (long long)blockIdx.x / (long long)gridDim.x;
+    const long long hi = e_lo + span * (long long)(blockIdx.x + 1) / (long long)gridDim.x;
+    if (lo >= hi) return;  // uniform across the workgroup
+    if (threadIdx.x == 0) {
+        long long a = q0, b = q1;  // largest i in [q0, q1) with es[i] <= lo
+        while (b - a > 1) {
+            long long mid = (a + b) >> 1;
+            if (es[mid] <= lo) a = mid;
+            else b = mid;
+        }
+        L.next = a;
+    }
+    __syncthreads();
+    long long i0 = L.next;
+    for (long long s0 = lo; s0 < hi; s0 += kEbWin) {
+        const long long we = s0 + kEbWin < hi ? s0 + kEbWin : hi;
+        const int w = (int)(q1 - i0 < (long long)(kEbWin + 1) ? q1 - i0 : (long long)(kEbWin + 1));
+        for (int j = threadIdx.x; j < w; j += kBlock) {
+            long long i = i0 + j;
+            L.id[j] = ids[i];
+            L.es[j] = es[i];
+            L.rs[j] = rs[i];
+            L.p0[j] = P0 ? P0[i] : 0;
+            L.p1[j] = P1 ? P1[i] : 0;
+        }
+        __syncthreads();
+        bool act[kEbR];
+        int u[kEbR], own[kEbR];
+#pragma unroll
+        for (int r = 0; r < kEbR; ++r) {
+            long long x = s0 + r * kBlock + threadIdx.x;
+            act[r] = x < we;
+            int j = lds_owner(L.es, w, act[r] ? x : s0);
+            own[r] = j;
+            u[r] = act[r] ? cols[L.rs[j] + (x - L.es[j])] : 0;
+        }
+        f(act, u, own, L);
+        __syncthreads();
+        if (threadIdx.x == 0 && we < hi) L.next = i0 + lds_owner(L.es, w, we);
+        __syncthreads();
+        i0 = L.next;
+    }
+}
+
+__device__ __forceinline__ long long wave_incl_scan64(long long x) {
+    const int lane = lane_id();
+    for (int o = 1; o < kWave; o <<= 1) {
+        long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// 64-bit block-wide exclusive scan; `lds` holds kWavesPerBlock long longs.
+__device__ __forceinline__ long long block_excl_scan64(long long x, long long &total, long long *lds) {
+    const int w = threadIdx.x >> 6;
+    long long incl = wave_incl_scan64(x);
+    if (lane_id() == kWave - 1) lds[w] = incl;
+    __syncthreads();
+    long long before = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+        long long s = lds[i];
+        before += i < w ? s : 0;
+        total += s;
+    }
+    __syncthreads();
+    return before + incl - x;
+}
+
+// Frontier lists whose slot and edge-space reservations must stay in the same
+// order share one 64-bit counter: (edges << kSlotBits) | slots.
+constexpr int kSlotBits = 31;
+constexpr unsigned long long kSlotMask = (1ull << kSlotBits) - 1;
+
+// Wave-aggregated append of (id, row start rs, row length d) to a frontier
+// list with a packed counter; entries land at index (slot - slot_base).
+__device__ __forceinline__ void wave_push_packed(bool pred, int id, long long rs, long long d,
+                                                 unsigned long long *ctr,
+                                                 unsigned long long slot_base, int32_t *ids,
+                                                 long long *es, long long *rsa) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    if (!pred) d = 0;
+    long long dpre = wave_incl_scan64(d) - d;
+    long long dtot = __shfl(dpre + d, kWave - 1);
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long old = 0;
+    if (lane_id() == leader)
+        old = atomicAdd(ctr, ((unsigned long long)dtot << kSlotBits) | (unsigned long long)__popcll(mask));
+    old = __shfl(old, leader);
+    if (pred) {
+        unsigned long long i = (old & kSlotMask) + lane_rank(mask) - slot_base;
+        ids[i] = id;
+        es[i] = (long long)(old >> kSlotBits) + dpre;
+        rsa[i] = rs;
+    }
+}
+
+// One atomic per block: reserve `total` slots of a counter; all threads get
+// the base.  `lds64` is one LDS word.
+__device__ __forceinline__ unsigned long long block_reserve(int total, unsigned long long *ctr,
+                                                            unsigned long long *lds64) {
+    if (threadIdx.x == 0) lds64[0] = total ? atomicAdd(ctr, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    unsigned long long b = lds64[0];
+    __syncthreads();
+    return b;
+}
+
+__device__ __forceinline__ int block_min(int x, int *lds) {
+    x = wave_min(x);
+    if (lane_id() == 0) lds[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int r = lds[0];
+#pragma unroll
+    for (int i = 1; i < kWavesPerBlock; ++i) r = min(r, lds[i]);
+    __syncthreads();
+    return r;
+}
+
 // Host side --------------------------------------------------------------
 
 void set_error(const char *fmt, ...);
@@ -97,6 +513,17 @@ inline size_t carve_bytes(int64_t count, size_t elem) {
 
 // Small pinned host buffer for counter read-back (one per host thread).
 void *host_scratch(size_t bytes);
+
+// Cooperative launch of a persistent kernel with the largest co-resident grid
+// (capped at `max_per_cu` blocks per compute unit).  Returns the grid size
+// used in *blocks.
+int persistent_grid(const void *kernel, int block, int max_per_cu, int *blocks);
+
+// Wall-clock ticks for `seconds` (device wall clock rate).
+unsigned long long wall_ticks(double seconds);
+
+// Integer tuning knob read once from the environment (default if unset).
+int tune_int(const char *name, int dflt);
 
 // Optional per-launch HIP-event timing (pico_profile_enable).  prof_begin
 // returns a record index, or -1 when profiling is off on this host thread.

@@ -1,19 +1,22 @@
-// HistoCore (paper Section IV-B, Alg. 6) for gfx950.
+// HistoCore (paper Section IV-B, Alg. 6) for gfx950, as one persistent
+// cooperative kernel per decomposition.
 //
 // Index2core (Section II-A, Alg. 2): every vertex starts at its degree and
 // repeatedly replaces its estimate by the h-index of its neighbours'
 // estimates; the fixed point is the coreness.  HistoCore keeps, per vertex,
 // a histogram of the neighbours' current estimates, so a vertex that changes
-// many times never re-reads its adjacency to recompute the h-index.
+// many times never re-reads its adjacency to recompute its h-index.
 //
 // Histogram layout: bucket b (1 <= b <= deg(v)) of vertex v lives at
-// histo[off[v] + b - 1], so the histograms of all vertices form one int32
-// array of m entries aligned with the adjacency array.  For b < core[v] the
-// bucket counts neighbours whose estimate is exactly b; bucket core[v] counts
-// neighbours whose estimate is >= core[v], which is cnt(v) of Theorem 2;
-// buckets above core[v] are dead.
+// histo[off[v] + b - 1], so all histograms form one int32 array of m entries
+// aligned with the adjacency array.  For b < core[v] the bucket counts
+// neighbours whose estimate is exactly b; bucket core[v] counts neighbours
+// whose estimate is >= core[v], which is cnt(v) of Theorem 2; buckets above
+// core[v] are dead.  Every bucket index used is in [1, core[v]] with
+// core[v] <= deg(v), so all accesses stay inside v's segment.
 //
-// Phases (separate kernels, so each round sees the previous round's values):
+// Phases, separated by grid barriers so that each round sees the previous
+// round's values (synchronous rounds):
 //   InitHisto   bucket min(core[u], core[v]) of v counts neighbour u, with
 //               core = deg; the first frontier is {v : cnt(v) < core(v)}.
 //   SumHisto    for each frontier vertex, sum buckets from its old value
@@ -30,59 +33,58 @@
 // The loop stops when a round enqueues nobody.  By Theorem 2 each round's
 // frontier is exactly the set of vertices whose h-index changes in that
 // synchronous round.
+//
+// Edge balance.  Frontier entries record where their rows start in the
+// concatenation of the round's rows (reserved with the entry's slot through
+// one packed counter), so UpdateHisto gives every workgroup an equal slice of
+// the round's edges, whatever the degrees.
+#include <climits>
+
 #include "common.hpp"
 
 namespace pico {
 namespace {
 
-struct HcCounters {
-    unsigned long long fcount[2];  // frontier sizes, by round parity
-    unsigned long long heavy_n;    // heavy edge-chunk descriptors
-    unsigned long long hv_n;       // heavy vertices (InitHisto) / heavy sums (SumHisto)
-    unsigned long long upd_edges;  // statistics: adjacency entries read by UpdateHisto
-    unsigned long long upd_moves;  // statistics: histogram moves (two atomics each)
-    unsigned long long buckets;    // statistics: buckets summed by SumHisto
+constexpr int kSmall = 16;     // lane-serial work up to this many items
+constexpr int kLdsCap = 2048;  // InitHisto: LDS histogram per wave up to this degree
+constexpr int kInitCh = 1024;  // InitHisto: edges per heavy piece
+constexpr int kSumWave = 512;  // SumHisto: one wave up to this value, a workgroup above
+
+// Cumulative counters.  FET packs (edges << 31) | slots of the frontier lists.
+enum { FET = 0, H_TAIL, HS_TAIL, N_MOVES, N_EDGES, N_BUCKETS };
+
+struct HcState {
+    GridState g;
+    Line rounds, first_frontier, frontier_total;
+    Line phase[kNumPhases];
 };
 
-// SumHisto: a wave handles values up to this size; above, a workgroup does.
-constexpr int kSumWaveMax = 8192;
-constexpr int kGridCap = 4096;
+template <typename Off>
+struct HcArgs {
+    const Off *off;
+    const int32_t *cols;
+    long long n;
+    int32_t *core;  // the caller's output array: estimates converge in place
+    int32_t *histo;
+    int32_t *oldcore;
+    int32_t *F[2];     // frontier ids, by round parity
+    long long *FE[2];  // ... row start in the round's concatenated edge space
+    long long *FR[2];  // ... first CSR position of the row
+    int32_t *P0;       // per entry of the current round: new value
+    int32_t *P1;       // ... old value
+    int32_t *HS;       // ring of n: heavy InitHisto rows (vertex ids) / heavy sums (entries)
+    long long *H;      // ring of hcap heavy InitHisto pieces (v << 32 | piece)
+    long long hcap;
+    HcState *st;
+    unsigned long long limit;
+};
 
-int blocks_for(long long items) { return grid_for((items + kBlock - 1) / kBlock, kGridCap); }
+inline long long pieces_cap(int64_t m) { return m / kInitCh + m / kLdsCap + 64; }
 
-__global__ void hc_reset(HcCounters *c) {
-    c->fcount[0] = 0;
-    c->fcount[1] = 0;
-    c->heavy_n = 0;
-    c->hv_n = 0;
-    c->upd_edges = 0;
-    c->upd_moves = 0;
-    c->buckets = 0;
-}
-
-__device__ __forceinline__ void flush_count(long long x, unsigned long long *dst) {
-    long long t = wave_sum64(x);
-    if (lane_id() == 0 && t) atomicAdd(dst, (unsigned long long)t);
-}
-
-__global__ void hc_reset_round(HcCounters *c, int nxt) {
-    c->fcount[nxt] = 0;
-    c->heavy_n = 0;
-    c->hv_n = 0;
-}
-
-__device__ __forceinline__ int wave_max_i(int x) {
-    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
-    return x;
-}
-
-__device__ __forceinline__ int wave_incl_scan(int x) {
-    const int lane = lane_id();
-    for (int o = 1; o < kWave; o <<= 1) {
-        int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    return x;
+__global__ void hc_state_init(HcState *st) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(st);
+    const int words = (int)(sizeof(HcState) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0ull;
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -91,150 +93,22 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_init_core(const Off *__restrict__ off, long long n,
-                                                       int32_t *__restrict__ core) {
-    const long long stride = (long long)gridDim.x * kBlock;
-    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride)
-        core[v] = (int)(off[v + 1] - off[v]);
+__device__ __forceinline__ void flush_count(long long x, unsigned long long *dst) {
+    long long t = wave_sum64(x);
+    if (lane_id() == 0 && t) atomicAdd(dst, (unsigned long long)t);
 }
 
-// InitHisto for light and medium vertices; heavy ones are listed and their
-// segments handled by the chunk kernels below.
-template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_init_histo(const Off *__restrict__ off,
-                                                        const int32_t *__restrict__ cols, long long n,
-                                                        const int32_t *__restrict__ core,
-                                                        int32_t *__restrict__ histo,
-                                                        int32_t *__restrict__ F,
-                                                        HcCounters *__restrict__ cnt,
-                                                        long long *__restrict__ heavy,
-                                                        int32_t *__restrict__ hverts) {
-    __shared__ int lds_all[kWavesPerBlock][kLdsBuckets];
-    int *lds = lds_all[threadIdx.x >> 6];
-    const int lane = lane_id();
-    const long long stride = (long long)gridDim.x * kBlock;
-    for (long long base = (long long)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < n;
-         base += stride) {
-        long long v = base + lane;
-        bool valid = v < n;
-        int d = valid ? core[v] : 0;
-        long long e0 = valid ? (long long)off[v] : 0;
-        bool push = false;
-        if (valid && d > 0 && d <= kSmallDeg) {
-            // one lane owns v's segment: plain read-modify-write, no atomics
-            for (int j = 0; j < d; ++j) histo[e0 + j] = 0;
-            for (int j = 0; j < d; ++j) {
-                int u = cols[e0 + j];
-                int b = min(max(core[u], 1), d);  // core[u] >= 1 on a symmetric graph
-                histo[e0 + b - 1] += 1;
-            }
-            push = histo[e0 + d - 1] < d;
-        }
-        unsigned long long mm = __ballot(valid && d > kSmallDeg && d <= kLdsBuckets);
-        while (mm) {
-            int l = __ffsll(mm) - 1;
-            mm &= mm - 1;
-            int dd = __shfl(d, l);
-            long long a = __shfl(e0, l);
-            for (int j = lane; j < dd; j += kWave) lds[j] = 0;
-            wave_lds_sync();
-            for (int j = lane; j < dd; j += kWave) {
-                int u = cols[a + j];
-                atomicAdd(&lds[min(max(core[u], 1), dd) - 1], 1);
-            }
-            wave_lds_sync();
-            for (int j = lane; j < dd; j += kWave) histo[a + j] = lds[j];
-            int top = lds[dd - 1];
-            wave_lds_sync();
-            if (lane == l) push = top < dd;
-        }
-        long long s = wave_append(push, &cnt->fcount[0]);
-        if (push) F[s] = (int)v;
-        bool hv = valid && d > kLdsBuckets;
-        long long t = wave_append(hv, &cnt->hv_n);
-        if (hv) {
-            hverts[t] = (int)v;
-            long long nch = ((long long)d + kChunk - 1) / kChunk;
-            unsigned long long c0 = atomicAdd(&cnt->heavy_n, (unsigned long long)nch);
-            for (long long j = 0; j < nch; ++j) heavy[c0 + j] = (v << 32) | j;
-        }
-    }
+__device__ __forceinline__ long long wave_id_global() {
+    return (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
 }
 
-template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_init_heavy_zero(const long long *__restrict__ heavy,
-                                                             const HcCounters *__restrict__ cnt,
-                                                             const Off *__restrict__ off,
-                                                             int32_t *__restrict__ histo) {
-    const long long nh = (long long)cnt->heavy_n;
-    const long long nw = (long long)gridDim.x * kWavesPerBlock;
-    for (long long h = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); h < nh; h += nw) {
-        long long desc = heavy[h];
-        int v = (int)(desc >> 32);
-        long long j = desc & 0xffffffffll;
-        long long vb = (long long)off[v], ve = (long long)off[v + 1];
-        long long e0 = vb + j * kChunk, e1 = e0 + kChunk < ve ? e0 + kChunk : ve;
-        for (long long e = e0 + lane_id(); e < e1; e += kWave) histo[e] = 0;
-    }
-}
-
-template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_init_heavy_count(const long long *__restrict__ heavy,
-                                                              const HcCounters *__restrict__ cnt,
-                                                              const Off *__restrict__ off,
-                                                              const int32_t *__restrict__ cols,
-                                                              const int32_t *__restrict__ core,
-                                                              int32_t *histo) {
-    const long long nh = (long long)cnt->heavy_n;
-    const long long nw = (long long)gridDim.x * kWavesPerBlock;
-    for (long long h = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); h < nh; h += nw) {
-        long long desc = heavy[h];
-        int v = (int)(desc >> 32);
-        long long j = desc & 0xffffffffll;
-        long long vb = (long long)off[v], ve = (long long)off[v + 1];
-        int d = (int)(ve - vb);
-        long long e0 = vb + j * kChunk, e1 = e0 + kChunk < ve ? e0 + kChunk : ve;
-        for (long long e = e0 + lane_id(); e < e1; e += kWave) {
-            int u = cols[e];
-            atomicAdd(&histo[vb + min(max(core[u], 1), d) - 1], 1);
-        }
-    }
-}
-
-template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_init_heavy_check(const int32_t *__restrict__ hverts,
-                                                              const Off *__restrict__ off,
-                                                              const int32_t *__restrict__ core,
-                                                              const int32_t *__restrict__ histo,
-                                                              int32_t *__restrict__ F,
-                                                              HcCounters *__restrict__ cnt) {
-    const long long nv = (long long)cnt->hv_n;
-    const long long stride = (long long)gridDim.x * kBlock;
-    for (long long base = (long long)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < nv;
-         base += stride) {
-        long long i = base + lane_id();
-        bool push = false;
-        int v = 0;
-        if (i < nv) {
-            v = hverts[i];
-            int d = core[v];
-            push = histo[(long long)off[v] + d - 1] < d;
-        }
-        long long s = wave_append(push, &cnt->fcount[0]);
-        if (push) F[s] = v;
-    }
-}
-
-// Reverse summation by one wave over buckets top, top-1, ..., floor (Step II
-// of Fig. 6), starting from running sum `carry`, never below bucket `lowb`.
-// Returns the first bucket b with carry + sum(b..top) >= b, with that sum,
-// or b = 0 if none.
+// Reverse summation by one wave over buckets top, top-1, ..., lowb (Step II
+// of Fig. 6), starting from running sum `carry`.  Returns the first bucket b
+// with carry + sum(b..top) >= b, with that sum, or h = 0 if none.
 __device__ __forceinline__ void wave_reverse_sum(const int32_t *seg, int top, int lowb, int carry,
                                                  int &h, int &s) {
     const int lane = lane_id();
     h = 0;
-    s = carry;
     while (top >= lowb) {
         int b = top - lane;
         int val = (b >= lowb) ? seg[b - 1] : 0;
@@ -252,99 +126,211 @@ __device__ __forceinline__ void wave_reverse_sum(const int32_t *seg, int top, in
     s = carry;
 }
 
+// ---------------------------------------------------------------- InitHisto
+
 template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_sum(const int32_t *__restrict__ F, long long nf,
-                                                 const Off *__restrict__ off, int32_t *core,
-                                                 int32_t *__restrict__ oldcore, int32_t *histo,
-                                                 int32_t *__restrict__ hlist,
-                                                 HcCounters *__restrict__ cnt) {
+__device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long long *lds_scan_l,
+                           unsigned long long *lds64) {
+    GridState *gs = &a.st->g;
     const int lane = lane_id();
-    const long long stride = (long long)gridDim.x * kBlock;
-    long long nb = 0;
-    for (long long base = (long long)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < nf;
-         base += stride) {
+    // Block-uniform tiles of kBlock vertices (a wave takes 64 of them), so the
+    // frontier pushes of a tile cost one atomic.
+    for (long long tile = (long long)blockIdx.x * kBlock; tile < a.n;
+         tile += (long long)gridDim.x * kBlock) {
+        long long v = tile + threadIdx.x;
+        bool valid = v < a.n;
+        int d = valid ? a.core[v] : 0;
+        long long e0 = valid ? (long long)a.off[v] : 0;
+        bool push = false;
+        if (valid && d > 0 && d <= kSmall) {
+            // one lane owns v's segment: plain read-modify-write, no atomics
+            for (int j = 0; j < d; ++j) a.histo[e0 + j] = 0;
+            for (int j = 0; j < d; ++j) {
+                int u = a.cols[e0 + j];
+                int b = min(max(a.core[u], 1), d);  // core[u] >= 1 on a symmetric graph
+                a.histo[e0 + b - 1] += 1;
+            }
+            push = a.histo[e0 + d - 1] < d;
+        }
+        unsigned long long mm = __ballot(valid && d > kSmall && d <= kLdsCap);
+        while (mm) {
+            int l = __ffsll(mm) - 1;
+            mm &= mm - 1;
+            int dd = __shfl(d, l);
+            long long ea = __shfl(e0, l);
+            for (int j = lane; j < dd; j += kWave) lds[j] = 0;
+            wave_lds_sync();
+            for (int j = lane; j < dd; j += kWave) {
+                int u = a.cols[ea + j];
+                atomicAdd(&lds[min(max(a.core[u], 1), dd) - 1], 1);
+            }
+            wave_lds_sync();
+            for (int j = lane; j < dd; j += kWave) a.histo[ea + j] = lds[j];
+            int top = lds[dd - 1];
+            wave_lds_sync();
+            if (lane == l) push = top < dd;
+        }
+        int tot = 0;
+        long long etot = 0;
+        int pre = block_excl_scan(push ? 1 : 0, tot, lds_scan);
+        long long epre = block_excl_scan64(push ? (long long)d : 0ll, etot, lds_scan_l);
+        if (threadIdx.x == 0)
+            lds64[0] = tot ? atomicAdd(&gs->ctr[FET].v, ((unsigned long long)etot << kSlotBits) |
+                                                            (unsigned long long)tot)
+                           : 0ull;
+        __syncthreads();
+        const unsigned long long old = lds64[0];
+        __syncthreads();
+        if (push) {
+            unsigned long long i = (old & kSlotMask) + pre;
+            a.F[0][i] = (int)v;
+            a.FE[0][i] = (long long)(old >> kSlotBits) + epre;
+            a.FR[0][i] = e0;
+        }
+        bool hv = valid && d > kLdsCap;
+        long long t = wave_append(hv, &gs->ctr[HS_TAIL].v);
+        if (hv) {
+            a.HS[t] = (int)v;
+            long long np = ((long long)d + kInitCh - 1) / kInitCh;
+            unsigned long long b = atomicAdd(&gs->ctr[H_TAIL].v, (unsigned long long)np);
+            for (long long j = 0; j < np; ++j) a.H[(b + j) % a.hcap] = (v << 32) | j;
+        }
+    }
+}
+
+// Heavy InitHisto rows, piece by piece: zero (pass 0) or count (pass 1).
+template <typename Off>
+__device__ void init_heavy(const HcArgs<Off> &a, unsigned long long h0, unsigned long long h1,
+                           int pass) {
+    const long long nw = (long long)gridDim.x * kWavesPerBlock;
+    for (long long p = (long long)h0 + wave_id_global(); p < (long long)h1; p += nw) {
+        long long desc = a.H[p % a.hcap];
+        int v = (int)(desc >> 32);
+        long long j = desc & 0xffffffffll;
+        long long vb = (long long)a.off[v], ve = (long long)a.off[v + 1];
+        int d = (int)(ve - vb);
+        long long e0 = vb + j * kInitCh, e1 = e0 + kInitCh < ve ? e0 + kInitCh : ve;
+        for (long long e = e0 + lane_id(); e < e1; e += kWave) {
+            if (pass == 0) {
+                a.histo[e] = 0;
+            } else {
+                int u = a.cols[e];
+                atomicAdd(&a.histo[vb + min(max(a.core[u], 1), d) - 1], 1);
+            }
+        }
+    }
+}
+
+template <typename Off>
+__device__ void init_heavy_check(const HcArgs<Off> &a, unsigned long long s0, unsigned long long s1) {
+    GridState *gs = &a.st->g;
+    const long long nw = (long long)gridDim.x * kWavesPerBlock;
+    for (long long base = (long long)s0 + wave_id_global() * kWave; base < (long long)s1;
+         base += nw * kWave) {
+        long long i = base + lane_id();
+        bool push = false;
+        int v = 0, d = 0;
+        long long rs = 0;
+        if (i < (long long)s1) {
+            v = a.HS[i % a.n];
+            d = a.core[v];
+            rs = (long long)a.off[v];
+            push = a.histo[rs + d - 1] < d;
+        }
+        wave_push_packed(push, v, rs, d, &gs->ctr[FET].v, 0, a.F[0], a.FE[0], a.FR[0]);
+    }
+}
+
+// ---------------------------------------------------------------- SumHisto
+
+// Entry i of the round's frontier: the new value goes to core and P0[i], the
+// old one to oldcore and P1[i].
+template <typename Off>
+__device__ void sum_histo(const HcArgs<Off> &a, const int32_t *F, const long long *FR, long long nf,
+                          long long &nb) {
+    GridState *gs = &a.st->g;
+    const int lane = lane_id();
+    const long long nw = (long long)gridDim.x * kWavesPerBlock;
+    for (long long base = wave_id_global() * kWave; base < nf; base += nw * kWave) {
         long long i = base + lane;
         bool valid = i < nf;
         int v = 0, c_old = 0;
         long long e0 = 0;
         if (valid) {
             v = F[i];
-            c_old = core[v];
-            e0 = (long long)off[v];
+            c_old = a.core[v];
+            e0 = FR[i];
         }
-        if (valid && c_old <= kSmallDeg) {
+        if (valid && c_old <= kSmall) {
             int s = 0, k = c_old;
             for (; k >= 1; --k) {
-                s += histo[e0 + k - 1];
+                s += a.histo[e0 + k - 1];
                 if (s >= k) break;
             }
             if (k < 1) k = 0;  // unreachable for a symmetric simple graph
-            core[v] = k;
-            oldcore[v] = c_old;
-            if (k >= 1) histo[e0 + k - 1] = s;
+            a.core[v] = k;
+            a.oldcore[v] = c_old;
+            a.P0[i] = k;
+            a.P1[i] = c_old;
+            if (k >= 1) a.histo[e0 + k - 1] = s;
             nb += c_old - max(k, 1) + 1;
         }
-        unsigned long long mm = __ballot(valid && c_old > kSmallDeg && c_old <= kSumWaveMax);
+        unsigned long long mm = __ballot(valid && c_old > kSmall && c_old <= kSumWave);
         while (mm) {
             int l = __ffsll(mm) - 1;
             mm &= mm - 1;
             int vv = __shfl(v, l), cc = __shfl(c_old, l);
-            long long a = __shfl(e0, l);
+            long long ea = __shfl(e0, l);
+            long long ii = __shfl(i, l);
             int h, s;
-            wave_reverse_sum(histo + a, cc, 1, 0, h, s);
+            wave_reverse_sum(a.histo + ea, cc, 1, 0, h, s);
             if (lane == 0) {
-                core[vv] = h;
-                oldcore[vv] = cc;
-                if (h >= 1) histo[a + h - 1] = s;
+                a.core[vv] = h;
+                a.oldcore[vv] = cc;
+                a.P0[ii] = h;
+                a.P1[ii] = cc;
+                if (h >= 1) a.histo[ea + h - 1] = s;
                 nb += cc - max(h, 1) + 1;
             }
         }
-        bool hv = valid && c_old > kSumWaveMax;
-        long long t = wave_append(hv, &cnt->hv_n);
-        if (hv) hlist[t] = v;
+        bool hv = valid && c_old > kSumWave;
+        long long t = wave_append(hv, &gs->ctr[HS_TAIL].v);
+        if (hv) a.HS[t % a.n] = (int)i;
     }
-    flush_count(nb, &cnt->buckets);
 }
 
-// SumHisto for vertices with very large old values: a workgroup per vertex.
-// Each thread sums one slice of the bucket range; the slices' running sums
-// locate the slice holding the answer (carry + sum(b..top) - b decreases
-// strictly as b grows), and one wave finishes inside that slice.
+// SumHisto for large old values: a workgroup per frontier entry.  Each
+// thread sums one slice of the bucket range; carry + sum(b..top) - b falls
+// strictly as b grows, so the running sums at slice bottoms locate the slice
+// holding the answer, and one wave finishes inside it.
 template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_sum_heavy(const int32_t *__restrict__ hlist,
-                                                       HcCounters *__restrict__ cnt,
-                                                       const Off *__restrict__ off, int32_t *core,
-                                                       int32_t *__restrict__ oldcore,
-                                                       int32_t *histo) {
-    __shared__ int part[kBlock];
-    __shared__ int first_ok;
+__device__ void sum_heavy(const HcArgs<Off> &a, const int32_t *F, const long long *FR,
+                          unsigned long long s0, unsigned long long s1, int *part, int *first_ok) {
+    GridState *gs = &a.st->g;
     const int t = threadIdx.x;
-    const long long nh = (long long)cnt->hv_n;
-    for (long long j = blockIdx.x; j < nh; j += gridDim.x) {
-        int v = hlist[j];
-        int c_old = core[v];
-        long long e0 = (long long)off[v];
-        const int32_t *seg = histo + e0;
+    for (long long j = (long long)s0 + blockIdx.x; j < (long long)s1; j += gridDim.x) {
+        const int i = a.HS[j % a.n];
+        int v = F[i];
+        int c_old = a.core[v];
+        long long e0 = FR[i];
+        const int32_t *seg = a.histo + e0;
         int L = (c_old + kBlock - 1) / kBlock;
-        int hi_b = c_old - t * L;          // slice t covers buckets [lo_b, hi_b]
+        int hi_b = c_old - t * L;
         int lo_b = max(1, hi_b - L + 1);
         int sum = 0;
         for (int b = hi_b; b >= lo_b; --b) sum += seg[b - 1];
-        if (hi_b < 1) sum = 0;
         part[t] = sum;
-        if (t == 0) first_ok = kBlock;
+        if (t == 0) *first_ok = kBlock;
         __syncthreads();
-        // inclusive running sum over slices 0..t (highest buckets first)
         for (int o = 1; o < kBlock; o <<= 1) {
             int y = t >= o ? part[t - o] : 0;
             __syncthreads();
             part[t] += y;
             __syncthreads();
         }
-        bool ok = hi_b >= 1 && part[t] >= lo_b;
-        if (ok) atomicMin(&first_ok, t);
+        if (hi_b >= 1 && part[t] >= lo_b) atomicMin(first_ok, t);
         __syncthreads();
-        int ts = first_ok;
+        int ts = *first_ok;
         if (ts < kBlock && (t >> 6) == 0) {
             int top = c_old - ts * L;
             int lowb = max(1, top - L + 1);
@@ -352,210 +338,226 @@ __global__ __launch_bounds__(kBlock) void hc_sum_heavy(const int32_t *__restrict
             int h, s;
             wave_reverse_sum(seg, top, lowb, carry, h, s);
             if (t == 0) {
-                core[v] = h;
-                oldcore[v] = c_old;
-                if (h >= 1) histo[e0 + h - 1] = s;
-                atomicAdd(&cnt->buckets, (unsigned long long)(c_old - max(h, 1) + 1));
+                a.core[v] = h;
+                a.oldcore[v] = c_old;
+                a.P0[i] = h;
+                a.P1[i] = c_old;
+                if (h >= 1) a.histo[e0 + h - 1] = s;
+                atomicAdd(&gs->ctr[N_BUCKETS].v, (unsigned long long)(c_old - max(h, 1) + 1));
             }
         } else if (ts >= kBlock && t == 0) {
-            core[v] = 0;  // unreachable for a symmetric simple graph
-            oldcore[v] = c_old;
+            a.core[v] = 0;  // unreachable for a symmetric simple graph
+            a.oldcore[v] = c_old;
+            a.P0[i] = 0;
+            a.P1[i] = c_old;
         }
         __syncthreads();
     }
 }
 
-// UpdateHisto for one edge (v, u); every lane of the wave calls it together.
+// ---------------------------------------------------------------- UpdateHisto
+
+// kEbR edges (v, u) of UpdateHisto per thread, all threads together: the
+// neighbour values, then the offsets of the neighbours that move, then the
+// histogram updates, each for all edges before any result is used.  A
+// neighbour whose cnt falls below its value joins the next frontier.
 template <typename Off>
-__device__ __forceinline__ void hc_relax(bool active, int u, int cv, int ov,
-                                         const Off *__restrict__ off,
-                                         const int32_t *__restrict__ core, int32_t *histo,
-                                         int32_t *__restrict__ Fn, unsigned long long *fcnt,
+__device__ __forceinline__ void hc_relax(const bool (&act)[kEbR], const int (&u)[kEbR],
+                                         const int (&cv)[kEbR], const int (&ov)[kEbR],
+                                         const HcArgs<Off> &a, int nxt, unsigned long long fbase,
                                          long long &nmove) {
-    bool push = false;
-    if (active) {
-        int cu = core[u];
-        if (cu > cv && cv >= 1) {
-            long long hb = (long long)off[u] - 1;
-            int b = min(ov, cu);
-            int c = atomicSub(&histo[hb + b], 1);
-            atomicAdd(&histo[hb + cv], 1);
-            push = (ov >= cu) && (c == cu);
+    GridState *gs = &a.st->g;
+    int cu[kEbR];
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? a.core[u[r]] : 0;
+    bool mv[kEbR];
+    long long hb[kEbR];
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) {
+        mv[r] = act[r] && cu[r] > cv[r] && cv[r] >= 1;
+        hb[r] = mv[r] ? (long long)a.off[u[r]] - 1 : 0;
+    }
+    bool push[kEbR];
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) {
+        push[r] = false;
+        if (mv[r]) {
+            if (ov[r] >= cu[r]) {
+                // v leaves u's top bucket: the only case whose old count matters
+                int c = atomicSub(&a.histo[hb[r] + cu[r]], 1);
+                push[r] = c == cu[r];
+            } else {
+                atomicSub(&a.histo[hb[r] + ov[r]], 1);  // no return value needed
+            }
+            atomicAdd(&a.histo[hb[r] + cv[r]], 1);
             ++nmove;
         }
     }
-    long long s = wave_append(push, fcnt);
-    if (push) Fn[s] = u;
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) {
+        long long rs = hb[r] + 1, d = 0;
+        if (push[r]) d = (long long)a.off[u[r] + 1] - rs;
+        wave_push_packed(push[r], u[r], rs, d, &gs->ctr[FET].v, fbase, a.F[nxt], a.FE[nxt],
+                         a.FR[nxt]);
+    }
 }
 
 template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_update(const int32_t *__restrict__ F, long long nf,
-                                                    const Off *__restrict__ off,
-                                                    const int32_t *__restrict__ cols,
-                                                    const int32_t *__restrict__ core,
-                                                    const int32_t *__restrict__ oldcore,
-                                                    int32_t *histo, int32_t *__restrict__ Fn,
-                                                    HcCounters *__restrict__ cnt, int nxt,
-                                                    long long *__restrict__ heavy) {
-    const int lane = lane_id();
-    unsigned long long *fcnt = &cnt->fcount[nxt];
-    const long long stride = (long long)gridDim.x * kBlock;
-    long long nmove = 0, nedge = 0;
-    for (long long base = (long long)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < nf;
-         base += stride) {
-        long long i = base + lane;
-        bool valid = i < nf;
-        int v = 0, cv = 0, ov = 0;
-        long long e0 = 0, e1 = 0;
-        if (valid) {
-            v = F[i];
-            cv = core[v];
-            ov = oldcore[v];
-            e0 = (long long)off[v];
-            e1 = (long long)off[v + 1];
-        }
-        long long d = e1 - e0;
-        nedge += d;
-        bool small = d <= kSmallDeg;
-        int dj = small ? (int)d : 0;
-        int maxd = wave_max_i(dj);
-        for (int j = 0; j < maxd; ++j) {
-            bool act = j < dj;
-            int u = act ? cols[e0 + j] : 0;
-            hc_relax<Off>(act, u, cv, ov, off, core, histo, Fn, fcnt, nmove);
-        }
-        unsigned long long mm = __ballot(!small && d <= kHeavyDeg);
-        while (mm) {
-            int l = __ffsll(mm) - 1;
-            mm &= mm - 1;
-            long long a = __shfl(e0, l), b = __shfl(e1, l);
-            int cvv = __shfl(cv, l), ovv = __shfl(ov, l);
-            for (long long e = a; e < b; e += kWave) {
-                long long ee = e + lane;
-                bool act = ee < b;
-                int u = act ? cols[ee] : 0;
-                hc_relax<Off>(act, u, cvv, ovv, off, core, histo, Fn, fcnt, nmove);
-            }
-        }
-        if (d > kHeavyDeg) {
-            long long nch = (d + kChunk - 1) / kChunk;
-            unsigned long long s = atomicAdd(&cnt->heavy_n, (unsigned long long)nch);
-            for (long long j = 0; j < nch; ++j) heavy[s + j] = ((long long)v << 32) | j;
-        }
-    }
-    flush_count(nmove, &cnt->upd_moves);
-    flush_count(nedge, &cnt->upd_edges);
-}
+__global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
+    __shared__ int lds_all[kWavesPerBlock][kLdsCap];
+    __shared__ int part[kBlock];
+    __shared__ int first_ok;
+    __shared__ int lds_scan[kWavesPerBlock];
+    __shared__ long long lds_scan_l[kWavesPerBlock];
+    __shared__ unsigned long long lds64[1];
+    __shared__ unsigned long long snap[kNumCtr + 1];
+    __shared__ EbLds eb;
+    HcState *st = a.st;
+    GridState *gs = &st->g;
+    const unsigned nb = gridDim.x;
+    long long nmove = 0, nedge = 0, nbuck = 0;
+    unsigned long long bar = 0;
+    const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
+    PhaseClock clk;
+    if (timer) clk.start();
 
-template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_update_heavy(const long long *__restrict__ heavy,
-                                                          const Off *__restrict__ off,
-                                                          const int32_t *__restrict__ cols,
-                                                          const int32_t *__restrict__ core,
-                                                          const int32_t *__restrict__ oldcore,
-                                                          int32_t *histo, int32_t *__restrict__ Fn,
-                                                          HcCounters *__restrict__ cnt, int nxt) {
-    const long long nh = (long long)cnt->heavy_n;
-    const long long nw = (long long)gridDim.x * kWavesPerBlock;
-    long long nmove = 0;
-    for (long long h = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); h < nh; h += nw) {
-        long long desc = heavy[h];
-        int v = (int)(desc >> 32);
-        long long j = desc & 0xffffffffll;
-        int cv = core[v], ov = oldcore[v];
-        long long vb = (long long)off[v], ve = (long long)off[v + 1];
-        long long e0 = vb + j * kChunk, e1 = e0 + kChunk < ve ? e0 + kChunk : ve;
-        for (long long e = e0; e < e1; e += kWave) {
-            long long ee = e + lane_id();
-            bool act = ee < e1;
-            int u = act ? cols[ee] : 0;
-            hc_relax<Off>(act, u, cv, ov, off, core, histo, Fn, &cnt->fcount[nxt], nmove);
-        }
+    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < a.n;
+         v += (long long)gridDim.x * kBlock)
+        a.core[v] = (int)(a.off[v + 1] - a.off[v]);
+    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (timer) clk.lap(&st->phase[0].v);
+    init_histo<Off>(a, lds_all[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64);
+    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    const unsigned long long h_end = snap[H_TAIL], hs_end = snap[HS_TAIL];
+    init_heavy<Off>(a, 0, h_end, 0);
+    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    init_heavy<Off>(a, 0, h_end, 1);
+    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    init_heavy_check<Off>(a, 0, hs_end);
+    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (timer) clk.lap(&st->phase[1].v);
+
+    // Round r's frontier: entries [0, nf) of buffer r & 1, edge space [e0, e1).
+    unsigned long long fbase = 0, e0 = 0;
+    long long nf = (long long)(snap[FET] & kSlotMask);
+    unsigned long long e1 = snap[FET] >> kSlotBits;
+    const long long first = nf;
+    long long rounds = 0, ftotal = 0;
+    for (int r = 0; nf > 0; ++r) {
+        const int cur = r & 1, nxt = cur ^ 1;
+        ++rounds;
+        ftotal += nf;
+        const unsigned long long hs0 = snap[HS_TAIL];
+        sum_histo<Off>(a, a.F[cur], a.FR[cur], nf, nbuck);
+        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (timer) clk.lap(&st->phase[2].v);
+        sum_heavy<Off>(a, a.F[cur], a.FR[cur], hs0, snap[HS_TAIL], part, &first_ok);
+        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (timer) clk.lap(&st->phase[3].v);
+        const unsigned long long fnext = snap[FET] & kSlotMask;
+        nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? (long long)(e1 - e0) : 0;
+        edge_balanced(a.F[cur], a.FE[cur], a.FR[cur], a.P0, a.P1, 0, nf, (long long)e0, (long long)e1,
+                      a.cols, eb,
+                      [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR],
+                          EbLds &L) {
+                          int cvr[kEbR], ovr[kEbR];
+#pragma unroll
+                          for (int q = 0; q < kEbR; ++q) {
+                              cvr[q] = L.p0[own[q]];
+                              ovr[q] = L.p1[own[q]];
+                          }
+                          hc_relax<Off>(act, u, cvr, ovr, a, nxt, fnext, nmove);
+                      });
+        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (timer) clk.lap(&st->phase[4].v);
+        nf = (long long)((snap[FET] & kSlotMask) - fnext);
+        fbase = fnext;
+        e0 = e1;
+        e1 = snap[FET] >> kSlotBits;
     }
-    flush_count(nmove, &cnt->upd_moves);
+    (void)fbase;
+    flush_count(nmove, &gs->ctr[N_MOVES].v);
+    flush_count(nedge, &gs->ctr[N_EDGES].v);
+    flush_count(nbuck, &gs->ctr[N_BUCKETS].v);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rounds.v = (unsigned long long)rounds;
+        st->first_frontier.v = (unsigned long long)first;
+        st->frontier_total.v = (unsigned long long)ftotal;
+    }
 }
 
 }  // namespace
 
 size_t histocore_ws_bytes(int64_t n, int64_t m) {
-    return carve_bytes(m, 4) + carve_bytes(n, 4) * 4 + carve_bytes(heavy_capacity(m), 8) +
-           carve_bytes(1, sizeof(HcCounters));
+    return carve_bytes(m, 4) + carve_bytes(n, 4) * 6 + carve_bytes(n, 8) * 4 +
+           carve_bytes(pieces_cap(m), 8) + carve_bytes(1, sizeof(HcState));
 }
 
 template <typename Off>
 int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
-                  size_t ws_bytes, pico_stats *st, hipStream_t stream) {
+                  size_t ws_bytes, pico_stats *stats, hipStream_t stream) {
+    if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
+        set_error("m=%lld too large for the packed frontier counter", (long long)m);
+        return PICO_ENOTSUP;
+    }
     Carve cv{static_cast<char *>(ws), 0, ws_bytes};
-    int32_t *histo = cv.take<int32_t>(m);
-    int32_t *oldcore = cv.take<int32_t>(n);
-    int32_t *F[2] = {cv.take<int32_t>(n), cv.take<int32_t>(n)};
-    int32_t *hlist = cv.take<int32_t>(n);
-    long long *heavy = cv.take<long long>(heavy_capacity(m));
-    HcCounters *cnt = cv.take<HcCounters>(1);
-    if (!histo || !oldcore || !F[0] || !F[1] || !hlist || !heavy || !cnt) {
+    HcArgs<Off> a;
+    a.off = off;
+    a.cols = cols;
+    a.n = n;
+    a.core = out;
+    a.histo = cv.take<int32_t>(m);
+    a.oldcore = cv.take<int32_t>(n);
+    for (int b = 0; b < 2; ++b) {
+        a.F[b] = cv.take<int32_t>(n);
+        a.FE[b] = cv.take<long long>(n);
+        a.FR[b] = cv.take<long long>(n);
+    }
+    a.P0 = cv.take<int32_t>(n);
+    a.P1 = cv.take<int32_t>(n);
+    a.HS = cv.take<int32_t>(n);
+    a.hcap = pieces_cap(m);
+    a.H = cv.take<long long>(a.hcap);
+    a.st = cv.take<HcState>(1);
+    if ((m > 0 && !a.histo) || !a.oldcore || !a.F[0] || !a.F[1] || !a.FE[0] || !a.FE[1] || !a.FR[0] ||
+        !a.FR[1] || !a.P0 || !a.P1 || !a.HS || !a.H || !a.st) {
         set_error("HistoCore workspace too small (%zu bytes given, %zu needed)", ws_bytes,
                   histocore_ws_bytes(n, m));
         return PICO_ENOMEM;
     }
-    HcCounters *h = static_cast<HcCounters *>(host_scratch(sizeof(HcCounters)));
-    if (!h) return PICO_EHIP;
-    int32_t *core = out;  // the estimates converge in place to the coreness
-
-    PICO_LAUNCH("hc_reset", hc_reset, dim3(1), dim3(1), stream, cnt);
-    PICO_LAUNCH("hc_init_core", hc_init_core<Off>, dim3(blocks_for(n)), dim3(kBlock), stream, off,
-                (long long)n, core);
-    PICO_LAUNCH("hc_init_histo", hc_init_histo<Off>, dim3(blocks_for(n)), dim3(kBlock), stream, off,
-                cols, (long long)n, core, histo, F[0], cnt, heavy, hlist);
-    PICO_LAUNCH("hc_init_heavy", hc_init_heavy_zero<Off>, dim3(kGridCap), dim3(kBlock), stream,
-                heavy, cnt, off, histo);
-    PICO_LAUNCH("hc_init_heavy", hc_init_heavy_count<Off>, dim3(kGridCap), dim3(kBlock), stream,
-                heavy, cnt, off, cols, core, histo);
-    PICO_LAUNCH("hc_init_heavy", hc_init_heavy_check<Off>, dim3(64), dim3(kBlock), stream, hlist,
-                off, core, histo, F[0], cnt);
+    a.limit = wall_ticks(20.0);
+    int blocks = 0;
+    int rc = persistent_grid(reinterpret_cast<const void *>(hc_persistent<Off>), kBlock,
+                             tune_int("PICO_HC_BLOCKS_PER_CU", 2), &blocks);
+    if (rc) return rc;
+    PICO_LAUNCH("hc_state_init", hc_state_init, dim3(1), dim3(kBlock), stream, a.st);
     PICO_LAUNCH_CHECK();
-    PICO_HIP_TRY(hipMemcpyAsync(h, cnt, sizeof(HcCounters), hipMemcpyDeviceToHost, stream));
+    void *args[] = {&a};
+    int rec = prof_begin("hc_persistent", stream);
+    PICO_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(hc_persistent<Off>),
+                                            dim3(blocks), dim3(kBlock), args, 0, stream));
+    prof_end(rec, stream);
+    HcState *h = static_cast<HcState *>(host_scratch(sizeof(HcState)));
+    if (!h) return PICO_EHIP;
+    PICO_HIP_TRY(hipMemcpyAsync(h, a.st, sizeof(HcState), hipMemcpyDeviceToHost, stream));
     PICO_HIP_TRY(hipStreamSynchronize(stream));
-
-    long long nf = (long long)h->fcount[0];
-    const long long first_frontier = nf;
-    int cur = 0;
-    int64_t rounds = 0, frontier_total = 0;
-    while (nf > 0) {
-        // Every round lowers the value of each frontier vertex, so there are
-        // at most sum(deg) = m rounds; more means a malformed graph.
-        if (rounds > m) {
-            set_error("HistoCore made no progress after %lld rounds (malformed graph?)",
-                      (long long)rounds);
-            return PICO_EINVAL;
-        }
-        ++rounds;
-        frontier_total += nf;
-        int nxt = cur ^ 1;
-        PICO_LAUNCH("hc_reset", hc_reset_round, dim3(1), dim3(1), stream, cnt, nxt);
-        PICO_LAUNCH("hc_sum", hc_sum<Off>, dim3(blocks_for(nf)), dim3(kBlock), stream, F[cur], nf, off,
-                    core, oldcore, histo, hlist, cnt);
-        PICO_LAUNCH("hc_sum_heavy", hc_sum_heavy<Off>, dim3(256), dim3(kBlock), stream, hlist, cnt, off,
-                    core, oldcore, histo);
-        PICO_LAUNCH("hc_update", hc_update<Off>, dim3(blocks_for(nf)), dim3(kBlock), stream, F[cur],
-                    nf, off, cols, core, oldcore, histo, F[nxt], cnt, nxt, heavy);
-        PICO_LAUNCH("hc_update_heavy", hc_update_heavy<Off>, dim3(kGridCap), dim3(kBlock), stream,
-                    heavy, off, cols, core, oldcore, histo, F[nxt], cnt, nxt);
-        PICO_LAUNCH_CHECK();
-        PICO_HIP_TRY(hipMemcpyAsync(h, cnt, sizeof(HcCounters), hipMemcpyDeviceToHost, stream));
-        PICO_HIP_TRY(hipStreamSynchronize(stream));
-        nf = (long long)h->fcount[nxt];
-        cur = nxt;
+    if (h->g.error.v) {
+        set_error("HistoCore kernel stopped (error %llu; grid of %d blocks)",
+                  (unsigned long long)h->g.error.v, blocks);
+        return PICO_EHIP;
     }
-    if (st) {
-        st->iterations = rounds;
-        st->sub_rounds = rounds;
-        st->scans = 0;
-        st->frontier_total = frontier_total;
-        st->k_max = 0;
-        st->edges_scanned = (int64_t)h->upd_edges;
-        st->atomics = (int64_t)h->upd_moves;
-        st->buckets_scanned = (int64_t)h->buckets;
-        st->pushes_dynamic = frontier_total - first_frontier;
+    if (stats) {
+        stats->iterations = (int64_t)h->rounds.v;
+        stats->sub_rounds = (int64_t)h->rounds.v;
+        stats->scans = 0;
+        stats->frontier_total = (int64_t)h->frontier_total.v;
+        stats->k_max = 0;
+        stats->edges_scanned = (int64_t)h->g.ctr[N_EDGES].v;
+        stats->atomics = (int64_t)h->g.ctr[N_MOVES].v;
+        stats->buckets_scanned = (int64_t)h->g.ctr[N_BUCKETS].v;
+        stats->pushes_dynamic = (int64_t)(h->frontier_total.v - h->first_frontier.v);
+        const double tick_ms = 1.0 / (double)wall_ticks(1e-3);
+        for (int i = 0; i < kNumPhases; ++i) stats->phase_ms[i] = (double)h->phase[i].v * tick_ms;
     }
     return PICO_OK;
 }

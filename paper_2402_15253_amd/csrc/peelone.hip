@@ -1,5 +1,6 @@
 // PeelOne with the assertion decrement and the dynamic in-level frontier
-// (paper Section III, Alg. 4), for gfx950.
+// (paper Section III, Alg. 4), for gfx950, as one persistent cooperative
+// kernel per decomposition.
 //
 // Level k peels every residual vertex whose residual degree has reached k.
 // The working array `core` holds residual degrees; by Corollary 1 every
@@ -11,19 +12,32 @@
 // filters on core[u] > k (the test the paper puts before the atomic) and then
 // issues a plain fetch-and-subtract; the thread whose fetch returns exactly
 // k + 1 is the unique one that lowers u to k, so it alone asserts u into the
-// level's queue and records out[u] = k.  A racing decrement that lands below
-// k only touches a vertex already asserted at level k, whose final value is
-// held in `out`, and no vertex receives more than deg(u) decrements, so the
+// level's frontier and records out[u] = k.  A racing decrement that lands
+// below k only touches a vertex already asserted at level k, whose final value
+// is held in `out`, and no vertex receives more than deg(u) decrements, so the
 // counter never underflows.  The vector produced is the one the clamped atomic
-// gives, without compare-and-swap retry loops under hub contention.
+// gives, without compare-and-swap retry loops under hub contention.  The
+// filter may read a stale (larger) value cached before a concurrent
+// decrement; that only costs a wasted atomic, never a missed one.
 //
-// Dynamic frontier (Section III-C, step 3).  Asserted vertices are appended to
-// the same queue and drained in the same level, batch after batch, so the
-// level count equals the number of distinct coreness values.  A level whose
-// scan finds no vertex jumps k straight to the smallest surviving value.
+// Dynamic frontier (Section III-C, step 3).  An asserted vertex is processed
+// in the same level.  While the work it brings is small, the workgroup that
+// asserted it expands it at once from an LDS queue, so peel chains advance
+// without any grid-wide step; larger bursts go to the global frontier list,
+// which the whole grid shares out in the level's next round, one grid
+// barrier later.  The level ends at the first barrier after which the global
+// list has nothing new.  A level whose scan finds nobody jumps k straight to
+// the smallest surviving value.
 //
-// Every vertex enters the queue exactly once over the whole run, so the queue
-// is one array of n entries holding the peel order.
+// Edge balance.  Each global frontier entry records where its adjacency row
+// starts in the concatenation of the round's rows, reserved together with the
+// entry's slot through one packed counter, so a round hands every workgroup
+// an equal slice of the round's edges however skewed the degrees are (the
+// load balancing the paper takes from Tigr, Section V-A).  Every thread keeps
+// four edges in flight to hide memory latency.
+//
+// Every vertex enters a frontier exactly once over the whole run, so the
+// global list needs at most n entries.
 #include <climits>
 
 #include "common.hpp"
@@ -31,316 +45,433 @@
 namespace pico {
 namespace {
 
-struct PoCounters {
-    unsigned long long qtail;    // vertices asserted into the peel queue so far
-    unsigned long long na_next;  // survivors written by the current scan
-    unsigned long long heavy_n;  // heavy edge-chunk descriptors of the current batch
-    unsigned long long atomics;  // decrements issued (statistics)
-    int minnext;                 // smallest surviving value above k seen by the scan
-    int pad;
+constexpr int kLq = 2048;          // LDS continuation queue per workgroup
+constexpr int kLocalMax = 4096;    // an LDS batch is expanded locally up to this many edges
+constexpr int kTile = kBlock * 8;  // scan items per block step
+
+// Cumulative counters of the grid state.  QET packs (edges << 31) | slots of
+// the global frontier list.
+enum { QET = 0, N_ATOM, N_DYN };
+
+struct PoState {
+    GridState g;
+    Line na[3];  // survivors listed by scan j, in slot j % 3
+    Line mn[3];  // smallest surviving value seen by scan j
+    Line levels, scans, kmax, rounds, peelable;
+    Line phase[kNumPhases];
 };
 
-__global__ void po_reset_scan(PoCounters *c) {
-    c->na_next = 0;
-    c->minnext = INT_MAX;
-}
-
-__global__ void po_reset_all(PoCounters *c) {
-    c->qtail = 0;
-    c->na_next = 0;
-    c->heavy_n = 0;
-    c->atomics = 0;
-    c->minnext = INT_MAX;
-}
-
-__global__ void po_reset_heavy(PoCounters *c) { c->heavy_n = 0; }
-
-__device__ __forceinline__ void scan_one(bool valid, int v, int c, int k, int32_t *__restrict__ out,
-                                         int32_t *__restrict__ Q, int32_t *__restrict__ A_next,
-                                         PoCounters *__restrict__ cnt, int &local_min) {
-    bool fr = valid && c == k;
-    bool sv = valid && c > k;
-    long long s = wave_append(fr, &cnt->qtail);
-    if (fr) {
-        Q[s] = v;
-        out[v] = k;
-    }
-    long long t = wave_append(sv, &cnt->na_next);
-    if (sv) {
-        A_next[t] = v;
-        local_min = min(local_min, c);
-    }
-}
-
-// First scan over all vertex ids: core[v] = deg(v) (Alg. 4, initial step),
-// isolated vertices get coreness 0, frontier = {deg == k}, survivors listed.
 template <typename Off>
-__global__ __launch_bounds__(kBlock) void po_first_scan(const Off *__restrict__ off, long long n,
-                                                        int32_t *__restrict__ core,
-                                                        int32_t *__restrict__ out, int k,
-                                                        int32_t *__restrict__ Q,
-                                                        int32_t *__restrict__ A_next,
-                                                        PoCounters *__restrict__ cnt) {
-    const long long stride = (long long)gridDim.x * kBlock;
-    int local_min = INT_MAX;
-    for (long long base = (long long)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < n;
-         base += stride) {
-        long long i = base + lane_id();
-        bool valid = i < n;
-        int c = -1;
-        if (valid) {
-            c = (int)(off[i + 1] - off[i]);
-            core[i] = c;
-            if (c == 0) out[i] = 0;
-        }
-        scan_one(valid && c > 0, (int)i, c, k, out, Q, A_next, cnt, local_min);
-    }
-    local_min = wave_min(local_min);
-    if (lane_id() == 0 && local_min != INT_MAX) atomicMin(&cnt->minnext, local_min);
+struct PoArgs {
+    const Off *off;
+    const int32_t *cols;
+    long long n;
+    int32_t *core;
+    int32_t *out;
+    int32_t *A0;
+    int32_t *A1;
+    int32_t *Q;      // global frontier list: vertex ids
+    long long *QE;   // ... start of each entry's row in the concatenated edge space
+    long long *QR;   // ... first CSR position of each entry's row
+    PoState *st;
+    unsigned long long limit;  // wall-clock ticks any single wait may last
+};
+
+__global__ void po_state_init(PoState *st) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(st);
+    const int words = (int)(sizeof(PoState) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0ull;
+    __syncthreads();
+    if (threadIdx.x < 3) st->mn[threadIdx.x].v = (unsigned long long)INT_MAX;
 }
 
-// Level scan over the survivor list of the previous scan (Alg. 4, scan
-// kernel).  Entries peeled since then hold values below k and drop out.
-__global__ __launch_bounds__(kBlock) void po_scan(const int32_t *__restrict__ A, long long nA,
-                                                  const int32_t *__restrict__ core,
-                                                  int32_t *__restrict__ out, int k,
-                                                  int32_t *__restrict__ Q,
-                                                  int32_t *__restrict__ A_next,
-                                                  PoCounters *__restrict__ cnt) {
-    const long long stride = (long long)gridDim.x * kBlock;
-    int local_min = INT_MAX;
-    for (long long base = (long long)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < nA;
-         base += stride) {
-        long long i = base + lane_id();
-        bool valid = i < nA;
-        int v = 0, c = -1;
-        if (valid) {
-            v = A[i];
-            c = core[v];
-        }
-        scan_one(valid, v, c, k, out, Q, A_next, cnt, local_min);
-    }
-    local_min = wave_min(local_min);
-    if (lane_id() == 0 && local_min != INT_MAX) atomicMin(&cnt->minnext, local_min);
-}
+// The workgroup's LDS continuation queue: a ring of kLq vertex ids.  `take`
+// is the next entry to hand out; `keep` the oldest entry still being read
+// (entries are consumed in workgroup-wide batches).
+struct LdsQueue {
+    int *buf;
+    unsigned *take;
+    unsigned *tail;
+    unsigned *keep;
+};
 
-// One edge of the scatter (Alg. 4, graph operator): neighbour u of a peeled
-// vertex.  Called by every lane of a wave together (`active` masks lanes out).
-__device__ __forceinline__ void po_relax(bool active, int u, int k, int32_t *core,
-                                         int32_t *__restrict__ out, int32_t *__restrict__ Q,
-                                         PoCounters *__restrict__ cnt, int &natom) {
-    bool push = false;
-    if (active) {
-        int cu = core[u];
-        if (cu > k) {
-            int old = atomicSub(&core[u], 1);
-            push = (old == k + 1);
-            ++natom;
-        }
-    }
-    long long s = wave_append(push, &cnt->qtail);
-    if (push) {
-        Q[s] = u;
-        out[u] = k;
-    }
-}
-
-__device__ __forceinline__ int wave_max_i(int x) {
-    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
-    return x;
-}
-
-__device__ __forceinline__ void flush_count(int natom, unsigned long long *dst) {
-    long long t = wave_sum64(natom);
-    if (lane_id() == 0 && t) atomicAdd(dst, (unsigned long long)t);
-}
-
-// Scatter of queue batch Q[lo, hi): a lane per low-degree vertex, a wave per
-// medium vertex, and fixed-size edge chunks for heavy vertices (emitted as
-// descriptors for po_heavy).
 template <typename Off>
-__global__ __launch_bounds__(kBlock) void po_scatter(long long lo, long long hi,
-                                                     const Off *__restrict__ off,
-                                                     const int32_t *__restrict__ cols,
-                                                     int32_t *core, int32_t *__restrict__ out,
-                                                     int k, int32_t *Q,
-                                                     PoCounters *__restrict__ cnt,
-                                                     long long *__restrict__ heavy) {
-    const long long stride = (long long)gridDim.x * kBlock;
-    int natom = 0;
-    for (long long base = lo + (long long)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1)); base < hi;
-         base += stride) {
-        long long i = base + lane_id();
-        bool valid = i < hi;
-        int v = 0;
-        long long e0 = 0, e1 = 0;
-        if (valid) {
-            v = Q[i];
-            e0 = (long long)off[v];
-            e1 = (long long)off[v + 1];
-        }
-        long long d = e1 - e0;
-        bool small = d <= kSmallDeg;
-        int dj = small ? (int)d : 0;
-        int maxd = wave_max_i(dj);
-        for (int j = 0; j < maxd; ++j) {
-            bool act = j < dj;
-            int u = act ? cols[e0 + j] : 0;
-            po_relax(act, u, k, core, out, Q, cnt, natom);
-        }
-        unsigned long long mm = __ballot(!small && d <= kHeavyDeg);
-        while (mm) {
-            int l = __ffsll(mm) - 1;
-            mm &= mm - 1;
-            long long a = __shfl(e0, l), b = __shfl(e1, l);
-            for (long long e = a; e < b; e += kWave) {
-                long long ee = e + lane_id();
-                bool act = ee < b;
-                int u = act ? cols[ee] : 0;
-                po_relax(act, u, k, core, out, Q, cnt, natom);
+struct PoCtx {
+    const Off *off;
+    int32_t *core;
+    int32_t *out;
+    int32_t *Q;
+    long long *QE;
+    long long *QR;
+    unsigned long long *qet;  // packed global frontier counter
+    LdsQueue lq;
+    int k;
+    int natom;
+    int ndyn;
+};
+
+// Append the lanes' vertices to the global frontier list (one atomic per
+// wave), with their row starts in the concatenated edge space.
+template <typename Off>
+__device__ __forceinline__ void push_global(bool pred, int u, PoCtx<Off> &c) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    long long rs = 0, d = 0;
+    if (pred) {
+        rs = (long long)c.off[u];
+        d = (long long)c.off[u + 1] - rs;
+    }
+    long long dpre = wave_incl_scan64(d) - d;
+    long long dtot = __shfl(dpre + d, kWave - 1);
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long old = 0;
+    if (lane_id() == leader)
+        old = atomicAdd(c.qet, ((unsigned long long)dtot << kSlotBits) | (unsigned long long)__popcll(mask));
+    old = __shfl(old, leader);
+    if (pred) {
+        unsigned long long slot = (old & kSlotMask) + lane_rank(mask);
+        c.Q[slot] = u;
+        c.QE[slot] = (long long)(old >> kSlotBits) + dpre;
+        c.QR[slot] = rs;
+    }
+}
+
+// Assert the lanes' vertices into the level's frontier: the workgroup's LDS
+// queue while it has room, else the global list for the next round.
+template <typename Off>
+__device__ __forceinline__ void enqueue(bool pred, int u, PoCtx<Off> &c) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    const unsigned cnt = (unsigned)__popcll(mask);
+    int global = 0;
+    unsigned base = 0;
+    if (lane_id() == leader) {
+        while (true) {
+            unsigned t = *(volatile unsigned *)c.lq.tail;
+            if (t + cnt - *(volatile unsigned *)c.lq.keep > (unsigned)kLq) {
+                global = 1;
+                break;
+            }
+            if (atomicCAS(c.lq.tail, t, t + cnt) == t) {
+                base = t;
+                break;
             }
         }
-        if (d > kHeavyDeg) {
-            long long nch = (d + kChunk - 1) / kChunk;
-            unsigned long long s = atomicAdd(&cnt->heavy_n, (unsigned long long)nch);
-            for (long long j = 0; j < nch; ++j) heavy[s + j] = ((long long)v << 32) | j;
-        }
     }
-    flush_count(natom, &cnt->atomics);
+    global = __shfl(global, leader);
+    base = __shfl(base, leader);
+    c.ndyn += pred ? 1 : 0;
+    if (global) {
+        push_global(pred, u, c);
+    } else if (pred) {
+        c.lq.buf[(base + lane_rank(mask)) % kLq] = u;
+    }
 }
 
-// Heavy-vertex edge chunks of the current batch, one wave per chunk.
+// kEbR edges per thread of the scatter (Alg. 4, graph operator): the filter
+// reads and the decrements of all edges are issued before any result is used.
 template <typename Off>
-__global__ __launch_bounds__(kBlock) void po_heavy(const long long *__restrict__ heavy,
-                                                   const Off *__restrict__ off,
-                                                   const int32_t *__restrict__ cols,
-                                                   int32_t *core, int32_t *__restrict__ out,
-                                                   int k, int32_t *Q,
-                                                   PoCounters *__restrict__ cnt) {
-    const long long nh = (long long)cnt->heavy_n;
-    const long long nw = (long long)gridDim.x * kWavesPerBlock;
-    int natom = 0;
-    for (long long h = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); h < nh; h += nw) {
-        long long desc = heavy[h];
-        int v = (int)(desc >> 32);
-        long long j = desc & 0xffffffffll;
-        long long vb = (long long)off[v], ve = (long long)off[v + 1];
-        long long e0 = vb + j * kChunk;
-        long long e1 = e0 + kChunk < ve ? e0 + kChunk : ve;
-        for (long long e = e0; e < e1; e += kWave) {
-            long long ee = e + lane_id();
-            bool act = ee < e1;
-            int u = act ? cols[ee] : 0;
-            po_relax(act, u, k, core, out, Q, cnt, natom);
+__device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kEbR], PoCtx<Off> &c) {
+    int cu[kEbR];
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? c.core[u[r]] : 0;
+    int old[kEbR];
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) {
+        old[r] = 0;
+        if (act[r] && cu[r] > c.k) {
+            old[r] = atomicSub(&c.core[u[r]], 1);
+            ++c.natom;
         }
     }
-    flush_count(natom, &cnt->atomics);
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) {
+        bool push = act[r] && old[r] == c.k + 1;
+        if (push) c.out[u[r]] = c.k;
+        enqueue(push, u[r], c);
+    }
 }
 
-constexpr int kGridCap = 4096;
+// Scan of a vertex list at level k (Alg. 4, scan kernel), block-aggregated:
+// frontier {core == k} to the global list, survivors {core > k} to the next
+// list, and the smallest surviving value.  With kInit it scans all ids 0..n-1
+// and sets core = deg, gives isolated vertices coreness 0 and lists every
+// other vertex.
+template <typename Off, bool kInit>
+__device__ void po_scan(const PoArgs<Off> &a, const int32_t *__restrict__ src, long long nsrc, int k,
+                        int32_t *__restrict__ dst, unsigned long long *na_ctr,
+                        unsigned long long *mn_ctr, int *lds, long long *lds_l,
+                        unsigned long long *lds64) {
+    GridState *gs = &a.st->g;
+    int lmin = INT_MAX;
+    const long long step = (long long)gridDim.x * kTile;
+    for (long long tile = (long long)blockIdx.x * kTile; tile < nsrc; tile += step) {
+        int vv[8];
+        unsigned fr = 0, sv = 0;
+        long long dsum = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            long long i = tile + r * kBlock + threadIdx.x;
+            int v = -1, c = -1;
+            if (i < nsrc) {
+                if (kInit) {
+                    v = (int)i;
+                    c = (int)(a.off[i + 1] - a.off[i]);
+                    a.core[i] = c;
+                    if (c == 0) a.out[i] = 0;
+                } else {
+                    v = src[i];
+                    c = a.core[v];
+                }
+            }
+            vv[r] = v;
+            if (!kInit && c == k) {
+                fr |= 1u << r;
+                dsum += (long long)(a.off[v + 1] - a.off[v]);
+            }
+            if (kInit ? c > 0 : c > k) {
+                sv |= 1u << r;
+                lmin = min(lmin, c);
+            }
+        }
+        int ts = 0;
+        int ps = block_excl_scan(__popc(sv), ts, lds);
+        unsigned long long bs = block_reserve(ts, na_ctr, lds64);
+        if (!kInit) {
+            int tf = 0;
+            long long te = 0;
+            int pf = block_excl_scan(__popc(fr), tf, lds);
+            long long pe = block_excl_scan64(dsum, te, lds_l);
+            if (threadIdx.x == 0)
+                lds64[0] = tf ? atomicAdd(&gs->ctr[QET].v,
+                                          ((unsigned long long)te << kSlotBits) | (unsigned long long)tf)
+                              : 0ull;
+            __syncthreads();
+            const unsigned long long old = lds64[0];
+            __syncthreads();
+            const unsigned long long bq = old & kSlotMask;
+            const long long be = (long long)(old >> kSlotBits);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if (fr >> r & 1u) {
+                    int v = vv[r];
+                    long long rs = (long long)a.off[v];
+                    a.out[v] = k;
+                    a.Q[bq + pf] = v;
+                    a.QE[bq + pf] = be + pe;
+                    a.QR[bq + pf] = rs;
+                    ++pf;
+                    pe += (long long)a.off[v + 1] - rs;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (sv >> r & 1u) dst[bs + ps++] = vv[r];
+    }
+    int bm = block_min(lmin, lds);
+    if (threadIdx.x == 0 && bm != INT_MAX) atomicMin(mn_ctr, (unsigned long long)bm);
+}
 
-int blocks_for(long long items) { return grid_for((items + kBlock - 1) / kBlock, kGridCap); }
+// One round of level k: this workgroup's slice of the edges of global
+// frontier entries [q0, q1) (edge space [e0, e1)), then everything it asserts
+// on the way, from its LDS queue: small batches expanded here, large ones
+// sent to the global list for the next round.
+template <typename Off>
+__device__ void po_round(const PoArgs<Off> &a, PoCtx<Off> &c, unsigned long long q0,
+                         unsigned long long q1, unsigned long long e0, unsigned long long e1,
+                         EbLds &E, ExpandLds &X) {
+    edge_balanced(a.Q, a.QE, a.QR, nullptr, nullptr, (long long)q0, (long long)q1, (long long)e0,
+                  (long long)e1, a.cols, E,
+                  [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&)[kEbR], EbLds &) {
+                      relax<Off>(act, u, c);
+                  });
+    while (true) {
+        __syncthreads();
+        const unsigned tk = *c.lq.take, tl = *c.lq.tail;
+        if (tl == tk) break;
+        const unsigned cnt = tl - tk < (unsigned)kBlock ? tl - tk : (unsigned)kBlock;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            *c.lq.keep = tk;
+            *c.lq.take = tk + cnt;
+        }
+        __syncthreads();
+        int v = -1;
+        long long rs = 0, d = 0;
+        if (threadIdx.x < cnt) {
+            v = c.lq.buf[(tk + threadIdx.x) % kLq];
+            rs = (long long)a.off[v];
+            d = (long long)a.off[v + 1] - rs;
+        }
+        long long tot = 0;
+        (void)block_excl_scan64(d, tot, X.scan_l);
+        if (tot > kLocalMax) {
+            push_global(v >= 0, v, c);  // a burst: share it out next round
+        } else {
+            block_expand<kEbR>((int)d, rs, 0, 0, a.cols, X,
+                               [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&)[kEbR]) {
+                                   relax<Off>(act, u, c);
+                               });
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *c.lq.keep = *c.lq.take;
+    }
+}
+
+template <typename Off>
+__global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
+    __shared__ int lds[kWavesPerBlock];
+    __shared__ long long lds_l[kWavesPerBlock];
+    __shared__ unsigned long long lds64[1];
+    __shared__ unsigned long long snap[kNumCtr + 1];
+    __shared__ int lq_buf[kLq];
+    __shared__ unsigned lq_take, lq_tail, lq_keep;
+    __shared__ EbLds eb;
+    __shared__ ExpandLds xl;
+    PoState *st = a.st;
+    GridState *gs = &st->g;
+    const unsigned nb = gridDim.x;
+    unsigned long long bar = 0;
+    if (threadIdx.x == 0) lq_take = lq_tail = lq_keep = 0;
+    PoCtx<Off> c{a.off, a.core, a.out, a.Q, a.QE, a.QR, &gs->ctr[QET].v,
+                 LdsQueue{lq_buf, &lq_take, &lq_tail, &lq_keep}, 0, 0, 0};
+
+    const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
+    PhaseClock clk;
+    if (timer) clk.start();
+    // Phase 0: core = deg, list of non-isolated vertices, smallest degree.
+    po_scan<Off, true>(a, nullptr, a.n, 0, a.A0, &st->na[0].v, &st->mn[0].v, lds, lds_l, lds64);
+    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (timer) clk.lap(&st->phase[0].v);
+    const unsigned long long peelable = ld_rlx(&st->na[0].v);
+    long long nprev = (long long)peelable;
+    c.k = (int)ld_rlx(&st->mn[0].v);
+    unsigned long long q_end = 0, e_end = 0;  // global list consumed so far
+    long long levels = 0, scans = 0, rounds = 0;
+    int kmax = 0;
+    unsigned long long scanned = 0;  // vertices found by level scans
+
+    for (int j = 1; peelable > 0; ++j) {
+        const int32_t *src = (j & 1) ? a.A0 : a.A1;
+        int32_t *dst = (j & 1) ? a.A1 : a.A0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st_rlx(&st->na[(j + 1) % 3].v, 0ull);
+            st_rlx(&st->mn[(j + 1) % 3].v, (unsigned long long)INT_MAX);
+        }
+        po_scan<Off, false>(a, src, nprev, c.k, dst, &st->na[j % 3].v, &st->mn[j % 3].v, lds, lds_l,
+                            lds64);
+        ++scans;
+        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (timer) clk.lap(&st->phase[1].v);
+        unsigned long long q1 = snap[QET] & kSlotMask, e1 = snap[QET] >> kSlotBits;
+        nprev = (long long)ld_rlx(&st->na[j % 3].v);
+        if (q1 == q_end) {  // empty level: jump to the smallest value left
+            if (nprev == 0) break;
+            c.k = (int)ld_rlx(&st->mn[j % 3].v);
+            continue;
+        }
+        scanned += q1 - q_end;
+        unsigned long long q0 = q_end, e0 = e_end;
+        while (q0 < q1) {
+            po_round<Off>(a, c, q0, q1, e0, e1, eb, xl);
+            ++rounds;
+            // fold this block's dynamic count in before the barrier's snapshot
+            long long t = wave_sum64(c.ndyn);
+            if (lane_id() == 0 && t) atomicAdd(&gs->ctr[N_DYN].v, (unsigned long long)t);
+            c.ndyn = 0;
+            if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+            q0 = q1;
+            e0 = e1;
+            q1 = snap[QET] & kSlotMask;
+            e1 = snap[QET] >> kSlotBits;
+        }
+        if (timer) clk.lap(&st->phase[2].v);
+        q_end = q1;
+        e_end = e1;
+        ++levels;
+        kmax = c.k;
+        // every vertex peeled so far was found by a scan or asserted once
+        if (scanned + snap[N_DYN] >= peelable) break;
+        c.k += 1;
+    }
+    long long t = wave_sum64(c.natom);
+    if (lane_id() == 0 && t) atomicAdd(&gs->ctr[N_ATOM].v, (unsigned long long)t);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->levels.v = (unsigned long long)levels;
+        st->scans.v = (unsigned long long)scans;
+        st->kmax.v = (unsigned long long)kmax;
+        st->rounds.v = (unsigned long long)rounds;
+        st->peelable.v = peelable;
+    }
+}
 
 }  // namespace
 
 size_t peelone_ws_bytes(int64_t n, int64_t m) {
-    return carve_bytes(n, 4) * 4 + carve_bytes(heavy_capacity(m), 8) + carve_bytes(1, sizeof(PoCounters));
+    return carve_bytes(n, 4) * 4 + carve_bytes(n, 8) * 2 + carve_bytes(1, sizeof(PoState));
 }
 
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
-                size_t ws_bytes, pico_stats *st, hipStream_t stream) {
+                size_t ws_bytes, pico_stats *stats, hipStream_t stream) {
+    if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
+        set_error("m=%lld too large for the packed frontier counter", (long long)m);
+        return PICO_ENOTSUP;
+    }
     Carve cv{static_cast<char *>(ws), 0, ws_bytes};
-    int32_t *core = cv.take<int32_t>(n);
-    int32_t *A[2] = {cv.take<int32_t>(n), cv.take<int32_t>(n)};
-    int32_t *Q = cv.take<int32_t>(n);
-    long long *heavy = cv.take<long long>(heavy_capacity(m));
-    PoCounters *cnt = cv.take<PoCounters>(1);
-    if (!core || !A[0] || !A[1] || !Q || !heavy || !cnt) {
+    PoArgs<Off> a;
+    a.off = off;
+    a.cols = cols;
+    a.n = n;
+    a.core = cv.take<int32_t>(n);
+    a.out = out;
+    a.A0 = cv.take<int32_t>(n);
+    a.A1 = cv.take<int32_t>(n);
+    a.Q = cv.take<int32_t>(n);
+    a.QE = cv.take<long long>(n);
+    a.QR = cv.take<long long>(n);
+    a.st = cv.take<PoState>(1);
+    if (!a.core || !a.A0 || !a.A1 || !a.Q || !a.QE || !a.QR || !a.st) {
         set_error("PeelOne workspace too small (%zu bytes given, %zu needed)", ws_bytes,
                   peelone_ws_bytes(n, m));
         return PICO_ENOMEM;
     }
-    PoCounters *h = static_cast<PoCounters *>(host_scratch(sizeof(PoCounters)));
-    if (!h) return PICO_EHIP;
-
-    auto readback = [&]() -> int {
-        PICO_HIP_TRY(hipMemcpyAsync(h, cnt, sizeof(PoCounters), hipMemcpyDeviceToHost, stream));
-        PICO_HIP_TRY(hipStreamSynchronize(stream));
-        return PICO_OK;
-    };
-
-    int k = 1;
-    int cur = 0;  // A[cur] receives the survivors of the next scan
-    PICO_LAUNCH("po_reset", po_reset_all, dim3(1), dim3(1), stream, cnt);
-    PICO_LAUNCH("po_scan", po_first_scan<Off>, dim3(blocks_for(n)), dim3(kBlock), stream, off,
-                (long long)n, core, out, k, Q, A[cur], cnt);
-    PICO_LAUNCH_CHECK();
-    int rc = readback();
+    a.limit = wall_ticks(20.0);
+    int blocks = 0;
+    int rc = persistent_grid(reinterpret_cast<const void *>(po_persistent<Off>), kBlock,
+                             tune_int("PICO_PO_BLOCKS_PER_CU", 1), &blocks);
     if (rc) return rc;
-    const unsigned long long peelable = h->qtail + h->na_next;
-    long long nA = (long long)h->na_next;
-    unsigned long long level_lo = 0;
-    int64_t levels = 0, batches = 0, scans = 1, dynamic = 0;
-    int kmax = 0;
+    PICO_LAUNCH("po_state_init", po_state_init, dim3(1), dim3(kBlock), stream, a.st);
+    PICO_LAUNCH_CHECK();
+    void *args[] = {&a};
+    int rec = prof_begin("po_persistent", stream);
+    PICO_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(po_persistent<Off>),
+                                            dim3(blocks), dim3(kBlock), args, 0, stream));
+    prof_end(rec, stream);
 
-    while (true) {
-        // Each pass either peels a level (k grows by one) or jumps k to a
-        // larger surviving value, so there are fewer than 2n + 2 passes.
-        if (scans > 2 * n + 2) {
-            set_error("PeelOne made no progress after %lld scans", (long long)scans);
-            return PICO_EINVAL;
-        }
-        unsigned long long lo = level_lo, hi = h->qtail;
-        if (hi == lo) {
-            // Empty level: every residual value exceeds k; jump to the smallest.
-            if (nA == 0) break;
-            k = h->minnext;
-        } else {
-            ++levels;
-            kmax = k;
-            unsigned long long level_scan_end = hi;
-            while (lo < hi) {
-                ++batches;
-                PICO_LAUNCH("po_reset", po_reset_heavy, dim3(1), dim3(1), stream, cnt);
-                PICO_LAUNCH("po_scatter", po_scatter<Off>, dim3(blocks_for((long long)(hi - lo))),
-                            dim3(kBlock), stream, (long long)lo, (long long)hi, off, cols, core, out,
-                            k, Q, cnt, heavy);
-                PICO_LAUNCH("po_heavy", po_heavy<Off>, dim3(kGridCap), dim3(kBlock), stream, heavy,
-                            off, cols, core, out, k, Q, cnt);
-                PICO_LAUNCH_CHECK();
-                rc = readback();
-                if (rc) return rc;
-                lo = hi;
-                hi = h->qtail;
-            }
-            dynamic += (int64_t)(h->qtail - level_scan_end);
-            if (h->qtail >= peelable) break;
-            k += 1;
-        }
-        // Scan the survivors of the previous scan at the new level.
-        const int32_t *src = A[cur];
-        cur ^= 1;
-        level_lo = h->qtail;
-        PICO_LAUNCH("po_reset", po_reset_scan, dim3(1), dim3(1), stream, cnt);
-        PICO_LAUNCH("po_scan", po_scan, dim3(blocks_for(nA)), dim3(kBlock), stream, src, nA, core,
-                    out, k, Q, A[cur], cnt);
-        PICO_LAUNCH_CHECK();
-        ++scans;
-        rc = readback();
-        if (rc) return rc;
-        nA = (long long)h->na_next;
+    PoState *h = static_cast<PoState *>(host_scratch(sizeof(PoState)));
+    if (!h) return PICO_EHIP;
+    PICO_HIP_TRY(hipMemcpyAsync(h, a.st, sizeof(PoState), hipMemcpyDeviceToHost, stream));
+    PICO_HIP_TRY(hipStreamSynchronize(stream));
+    if (h->g.error.v) {
+        set_error("PeelOne kernel stopped (error %llu; grid of %d blocks)",
+                  (unsigned long long)h->g.error.v, blocks);
+        return PICO_EHIP;
     }
-    if (st) {
-        st->iterations = levels;
-        st->sub_rounds = batches;
-        st->scans = scans;
-        st->frontier_total = (int64_t)h->qtail;
-        st->k_max = kmax;
-        st->edges_scanned = m;  // every peeled vertex scans its whole row once
-        st->atomics = (int64_t)h->atomics;
-        st->buckets_scanned = 0;
-        st->pushes_dynamic = dynamic;
+    if (stats) {
+        stats->iterations = (int64_t)h->levels.v;
+        stats->sub_rounds = (int64_t)h->rounds.v;
+        stats->scans = (int64_t)h->scans.v;
+        stats->frontier_total = (int64_t)h->peelable.v;
+        stats->k_max = (int32_t)h->kmax.v;
+        stats->edges_scanned = m;  // every peeled vertex scans its whole row once
+        stats->atomics = (int64_t)h->g.ctr[N_ATOM].v;
+        stats->buckets_scanned = 0;
+        stats->pushes_dynamic = (int64_t)h->g.ctr[N_DYN].v;
+        const double tick_ms = 1.0 / (double)wall_ticks(1e-3);
+        for (int i = 0; i < kNumPhases; ++i) stats->phase_ms[i] = (double)h->phase[i].v * tick_ms;
     }
     return PICO_OK;
 }
