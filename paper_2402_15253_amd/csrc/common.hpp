@@ -187,11 +187,11 @@ __device__ __forceinline__ void fence_acquire() {
 // with relaxed loads and fence once on the way out.
 //
 // `bar_no` counts the barriers this block has passed (the same sequence in
-// every block).  `on_release(gs)` runs on the releasing block after all have
+// every block).  Only the first NSNAP counters are snapshotted.  `on_release(gs)` runs on the releasing block after all have
 // arrived and before any is let go.  snap_out (LDS, kNumCtr + 1 entries)
 // receives the counters as they stood then, and the error flag.  Returns
 // false if the grid is in error.
-template <typename Rel = NoRelease>
+template <int NSNAP = kNumCtr, typename Rel = NoRelease>
 __device__ __forceinline__ bool grid_sync(GridState *gs, unsigned nblocks, unsigned long long limit,
                                           unsigned long long *snap_out, unsigned long long &bar_no,
                                           Rel on_release = Rel()) {
@@ -215,10 +215,13 @@ __device__ __forceinline__ bool grid_sync(GridState *gs, unsigned nblocks, unsig
             if (t == (b + 1) * ngroups) {
                 fence_acquire();
                 on_release(gs);
-                for (int i = 0; i < kNumCtr; ++i) {
-                    unsigned long long c = ld_rlx(&gs->ctr[i].v);
-                    st_rlx(&gs->snap[b & 1][i], c);
-                    snap_out[i] = c;
+                unsigned long long c[NSNAP > 0 ? NSNAP : 1];
+#pragma unroll
+                for (int i = 0; i < NSNAP; ++i) c[i] = ld_rlx(&gs->ctr[i].v);
+#pragma unroll
+                for (int i = 0; i < NSNAP; ++i) {
+                    st_rlx(&gs->snap[b & 1][i], c[i]);
+                    snap_out[i] = c[i];
                 }
                 fence_release();
                 st_rlx(&gs->gen.v, b + 1);
@@ -231,7 +234,8 @@ __device__ __forceinline__ bool grid_sync(GridState *gs, unsigned nblocks, unsig
                 if (w.stop(gs)) break;
             }
             fence_acquire();
-            for (int i = 0; i < kNumCtr; ++i) snap_out[i] = ld_rlx(&gs->snap[b & 1][i]);
+#pragma unroll
+            for (int i = 0; i < NSNAP; ++i) snap_out[i] = ld_rlx(&gs->snap[b & 1][i]);
         }
         snap_out[kNumCtr] = ld_rlx(&gs->error.v);
     }
@@ -342,8 +346,9 @@ __device__ __forceinline__ int lds_owner(const long long *es, int w, long long x
 
 // Process edges [e_lo, e_hi) of the concatenation of entries [q0, q1), this
 // workgroup's share being an equal slice.  P0/P1 (may be null) are per-entry
-// payloads copied to LDS.  f(act[kEbR], u[kEbR], own[kEbR], L) is called by
-// all threads together for each step; own indexes L's entry arrays.
+// payloads copied to LDS; aux (may be null) is a per-edge array read beside
+// cols.  f(act[kEbR], u[kEbR], own[kEbR], L, aux[kEbR]) is called by all
+// threads together for each step; own indexes L's entry arrays.
 template <typename F>
 __device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
                                               const long long *__restrict__ es,
@@ -351,7 +356,8 @@ __device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
                                               const int32_t *__restrict__ P0,
                                               const int32_t *__restrict__ P1, long long q0, long long q1,
                                               long long e_lo, long long e_hi,
-                                              const int32_t *__restrict__ cols, EbLds &L, F &&f) {
+                                              const int32_t *__restrict__ cols,
+                                              const int32_t *__restrict__ aux, EbLds &L, F &&f) {
     const long long span = e_hi - e_lo;
     const long long lo = e_lo + span * (long long)blockIdx.x / (long long)gridDim.x;
     const long long hi = e_lo + span * (long long)(blockIdx.x + 1) / (long long)gridDim.x;
@@ -380,16 +386,18 @@ __device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
         }
         __syncthreads();
         bool act[kEbR];
-        int u[kEbR], own[kEbR];
+        int u[kEbR], own[kEbR], ax[kEbR];
 #pragma unroll
         for (int r = 0; r < kEbR; ++r) {
             long long x = s0 + r * kBlock + threadIdx.x;
             act[r] = x < we;
             int j = lds_owner(L.es, w, act[r] ? x : s0);
             own[r] = j;
-            u[r] = act[r] ? cols[L.rs[j] + (x - L.es[j])] : 0;
+            long long e = L.rs[j] + (x - L.es[j]);
+            u[r] = act[r] ? cols[e] : 0;
+            ax[r] = (act[r] && aux) ? aux[e] : 0;
         }
-        f(act, u, own, L);
+        f(act, u, own, L, ax);
         __syncthreads();
         if (threadIdx.x == 0 && we < hi) L.next = i0 + lds_owner(L.es, w, we);
         __syncthreads();

@@ -52,6 +52,7 @@ constexpr int kSumWave = 512;  // SumHisto: one wave up to this value, a workgro
 
 // Cumulative counters.  FET packs (edges << 31) | slots of the frontier lists.
 enum { FET = 0, H_TAIL, HS_TAIL, N_MOVES, N_EDGES, N_BUCKETS };
+constexpr int kSnap = 3;  // counters read at barriers: FET, H_TAIL, HS_TAIL
 
 struct HcState {
     GridState g;
@@ -66,6 +67,7 @@ struct HcArgs {
     long long n;
     int32_t *core;  // the caller's output array: estimates converge in place
     int32_t *histo;
+    int32_t *ndeg;     // per adjacency entry: degree of the neighbour (written by InitHisto)
     int32_t *oldcore;
     int32_t *F[2];     // frontier ids, by round parity
     long long *FE[2];  // ... row start in the round's concatenated edge space
@@ -147,7 +149,9 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
             for (int j = 0; j < d; ++j) a.histo[e0 + j] = 0;
             for (int j = 0; j < d; ++j) {
                 int u = a.cols[e0 + j];
-                int b = min(max(a.core[u], 1), d);  // core[u] >= 1 on a symmetric graph
+                int du = a.core[u];
+                a.ndeg[e0 + j] = du;
+                int b = min(max(du, 1), d);  // core[u] >= 1 on a symmetric graph
                 a.histo[e0 + b - 1] += 1;
             }
             push = a.histo[e0 + d - 1] < d;
@@ -162,7 +166,9 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
             wave_lds_sync();
             for (int j = lane; j < dd; j += kWave) {
                 int u = a.cols[ea + j];
-                atomicAdd(&lds[min(max(a.core[u], 1), dd) - 1], 1);
+                int du = a.core[u];
+                a.ndeg[ea + j] = du;
+                atomicAdd(&lds[min(max(du, 1), dd) - 1], 1);
             }
             wave_lds_sync();
             for (int j = lane; j < dd; j += kWave) a.histo[ea + j] = lds[j];
@@ -215,7 +221,9 @@ __device__ void init_heavy(const HcArgs<Off> &a, unsigned long long h0, unsigned
                 a.histo[e] = 0;
             } else {
                 int u = a.cols[e];
-                atomicAdd(&a.histo[vb + min(max(a.core[u], 1), d) - 1], 1);
+                int du = a.core[u];
+                a.ndeg[e] = du;
+                atomicAdd(&a.histo[vb + min(max(du, 1), d) - 1], 1);
             }
         }
     }
@@ -362,11 +370,15 @@ __device__ void sum_heavy(const HcArgs<Off> &a, const int32_t *F, const long lon
 // histogram updates, each for all edges before any result is used.  A
 // neighbour whose cnt falls below its value joins the next frontier.
 template <typename Off>
-__device__ __forceinline__ void hc_relax(const bool (&act)[kEbR], const int (&u)[kEbR],
+__device__ __forceinline__ void hc_relax(const bool (&act0)[kEbR], const int (&u)[kEbR],
                                          const int (&cv)[kEbR], const int (&ov)[kEbR],
-                                         const HcArgs<Off> &a, int nxt, unsigned long long fbase,
-                                         long long &nmove) {
+                                         const int (&du)[kEbR], const HcArgs<Off> &a, int nxt,
+                                         unsigned long long fbase, long long &nmove) {
     GridState *gs = &a.st->g;
+    // A neighbour of degree <= cv has core[u] <= deg(u) <= cv: never moved.
+    bool act[kEbR];
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) act[r] = act0[r] && du[r] > cv[r];
     int cu[kEbR];
 #pragma unroll
     for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? a.core[u[r]] : 0;
@@ -424,17 +436,17 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
     for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < a.n;
          v += (long long)gridDim.x * kBlock)
         a.core[v] = (int)(a.off[v + 1] - a.off[v]);
-    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[0].v);
     init_histo<Off>(a, lds_all[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64);
-    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     const unsigned long long h_end = snap[H_TAIL], hs_end = snap[HS_TAIL];
     init_heavy<Off>(a, 0, h_end, 0);
-    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     init_heavy<Off>(a, 0, h_end, 1);
-    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     init_heavy_check<Off>(a, 0, hs_end);
-    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[1].v);
 
     // Round r's frontier: entries [0, nf) of buffer r & 1, edge space [e0, e1).
@@ -449,26 +461,26 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
         ftotal += nf;
         const unsigned long long hs0 = snap[HS_TAIL];
         sum_histo<Off>(a, a.F[cur], a.FR[cur], nf, nbuck);
-        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[2].v);
         sum_heavy<Off>(a, a.F[cur], a.FR[cur], hs0, snap[HS_TAIL], part, &first_ok);
-        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[3].v);
         const unsigned long long fnext = snap[FET] & kSlotMask;
         nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? (long long)(e1 - e0) : 0;
         edge_balanced(a.F[cur], a.FE[cur], a.FR[cur], a.P0, a.P1, 0, nf, (long long)e0, (long long)e1,
-                      a.cols, eb,
+                      a.cols, a.ndeg, eb,
                       [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR],
-                          EbLds &L) {
+                          EbLds &L, const int (&du)[kEbR]) {
                           int cvr[kEbR], ovr[kEbR];
 #pragma unroll
                           for (int q = 0; q < kEbR; ++q) {
                               cvr[q] = L.p0[own[q]];
                               ovr[q] = L.p1[own[q]];
                           }
-                          hc_relax<Off>(act, u, cvr, ovr, a, nxt, fnext, nmove);
+                          hc_relax<Off>(act, u, cvr, ovr, du, a, nxt, fnext, nmove);
                       });
-        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[4].v);
         nf = (long long)((snap[FET] & kSlotMask) - fnext);
         fbase = fnext;
@@ -489,7 +501,7 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
 }  // namespace
 
 size_t histocore_ws_bytes(int64_t n, int64_t m) {
-    return carve_bytes(m, 4) + carve_bytes(n, 4) * 6 + carve_bytes(n, 8) * 4 +
+    return carve_bytes(m, 4) * 2 + carve_bytes(n, 4) * 6 + carve_bytes(n, 8) * 4 +
            carve_bytes(pieces_cap(m), 8) + carve_bytes(1, sizeof(HcState));
 }
 
@@ -507,6 +519,7 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
     a.n = n;
     a.core = out;
     a.histo = cv.take<int32_t>(m);
+    a.ndeg = cv.take<int32_t>(m);
     a.oldcore = cv.take<int32_t>(n);
     for (int b = 0; b < 2; ++b) {
         a.F[b] = cv.take<int32_t>(n);
@@ -519,7 +532,7 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
     a.hcap = pieces_cap(m);
     a.H = cv.take<long long>(a.hcap);
     a.st = cv.take<HcState>(1);
-    if ((m > 0 && !a.histo) || !a.oldcore || !a.F[0] || !a.F[1] || !a.FE[0] || !a.FE[1] || !a.FR[0] ||
+    if ((m > 0 && (!a.histo || !a.ndeg)) || !a.oldcore || !a.F[0] || !a.F[1] || !a.FE[0] || !a.FE[1] || !a.FR[0] ||
         !a.FR[1] || !a.P0 || !a.P1 || !a.HS || !a.H || !a.st) {
         set_error("HistoCore workspace too small (%zu bytes given, %zu needed)", ws_bytes,
                   histocore_ws_bytes(n, m));

@@ -20,6 +20,15 @@
 // filter may read a stale (larger) value cached before a concurrent
 // decrement; that only costs a wasted atomic, never a missed one.
 //
+// Claims.  A level's scan and its scatter overlap (a workgroup expands what
+// its own scan found while others still scan), so each vertex is claimed by
+// exactly one thread with a compare-and-swap of out[v] from -1 to k: the
+// scanner that reads core[v] == k, or the decrementer whose fetch returns
+// k + 1 (it lowered v to k) or k (a stale filter read let it lower a
+// not-yet-claimed level-k vertex below k).  Every vertex whose value reaches
+// k or less during level k meets one of these, so none is lost, and the
+// compare-and-swap lets only one expand it.
+//
 // Dynamic frontier (Section III-C, step 3).  An asserted vertex is processed
 // in the same level.  While the work it brings is small, the workgroup that
 // asserted it expands it at once from an LDS queue, so peel chains advance
@@ -39,6 +48,9 @@
 // Every vertex enters a frontier exactly once over the whole run, so the
 // global list needs at most n entries.
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
 
 #include "common.hpp"
 
@@ -51,12 +63,14 @@ constexpr int kTile = kBlock * 8;  // scan items per block step
 
 // Cumulative counters of the grid state.  QET packs (edges << 31) | slots of
 // the global frontier list.
-enum { QET = 0, N_ATOM, N_DYN };
+enum { QET = 0, N_DYN, N_ATOM };
+constexpr int kSnap = 1;  // counters read at barriers: QET
 
 struct PoState {
     GridState g;
     Line na[3];  // survivors listed by scan j, in slot j % 3
     Line mn[3];  // smallest surviving value seen by scan j
+    Line nf[3];  // vertices claimed by scan j
     Line levels, scans, kmax, rounds, peelable;
     Line phase[kNumPhases];
 };
@@ -75,6 +89,8 @@ struct PoArgs {
     long long *QR;   // ... first CSR position of each entry's row
     PoState *st;
     unsigned long long limit;  // wall-clock ticks any single wait may last
+    long long *trace;          // optional per-level record (development aid), or null
+    int trace_cap;
 };
 
 __global__ void po_state_init(PoState *st) {
@@ -169,6 +185,10 @@ __device__ __forceinline__ void enqueue(bool pred, int u, PoCtx<Off> &c) {
     }
 }
 
+__device__ __forceinline__ bool claim_vertex(int32_t *out, int v, int k) {
+    return atomicCAS(&out[v], -1, k) == -1;
+}
+
 // kEbR edges per thread of the scatter (Alg. 4, graph operator): the filter
 // reads and the decrements of all edges are issued before any result is used.
 template <typename Off>
@@ -185,108 +205,21 @@ __device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kE
             ++c.natom;
         }
     }
+    bool push[kEbR];
 #pragma unroll
     for (int r = 0; r < kEbR; ++r) {
-        bool push = act[r] && old[r] == c.k + 1;
-        if (push) c.out[u[r]] = c.k;
-        enqueue(push, u[r], c);
+        push[r] = act[r] && cu[r] > c.k && (old[r] == c.k + 1 || old[r] == c.k) &&
+                  claim_vertex(c.out, u[r], c.k);
     }
+#pragma unroll
+    for (int r = 0; r < kEbR; ++r) enqueue(push[r], u[r], c);
 }
 
-// Scan of a vertex list at level k (Alg. 4, scan kernel), block-aggregated:
-// frontier {core == k} to the global list, survivors {core > k} to the next
-// list, and the smallest surviving value.  With kInit it scans all ids 0..n-1
-// and sets core = deg, gives isolated vertices coreness 0 and lists every
-// other vertex.
-template <typename Off, bool kInit>
-__device__ void po_scan(const PoArgs<Off> &a, const int32_t *__restrict__ src, long long nsrc, int k,
-                        int32_t *__restrict__ dst, unsigned long long *na_ctr,
-                        unsigned long long *mn_ctr, int *lds, long long *lds_l,
-                        unsigned long long *lds64) {
-    GridState *gs = &a.st->g;
-    int lmin = INT_MAX;
-    const long long step = (long long)gridDim.x * kTile;
-    for (long long tile = (long long)blockIdx.x * kTile; tile < nsrc; tile += step) {
-        int vv[8];
-        unsigned fr = 0, sv = 0;
-        long long dsum = 0;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            long long i = tile + r * kBlock + threadIdx.x;
-            int v = -1, c = -1;
-            if (i < nsrc) {
-                if (kInit) {
-                    v = (int)i;
-                    c = (int)(a.off[i + 1] - a.off[i]);
-                    a.core[i] = c;
-                    if (c == 0) a.out[i] = 0;
-                } else {
-                    v = src[i];
-                    c = a.core[v];
-                }
-            }
-            vv[r] = v;
-            if (!kInit && c == k) {
-                fr |= 1u << r;
-                dsum += (long long)(a.off[v + 1] - a.off[v]);
-            }
-            if (kInit ? c > 0 : c > k) {
-                sv |= 1u << r;
-                lmin = min(lmin, c);
-            }
-        }
-        int ts = 0;
-        int ps = block_excl_scan(__popc(sv), ts, lds);
-        unsigned long long bs = block_reserve(ts, na_ctr, lds64);
-        if (!kInit) {
-            int tf = 0;
-            long long te = 0;
-            int pf = block_excl_scan(__popc(fr), tf, lds);
-            long long pe = block_excl_scan64(dsum, te, lds_l);
-            if (threadIdx.x == 0)
-                lds64[0] = tf ? atomicAdd(&gs->ctr[QET].v,
-                                          ((unsigned long long)te << kSlotBits) | (unsigned long long)tf)
-                              : 0ull;
-            __syncthreads();
-            const unsigned long long old = lds64[0];
-            __syncthreads();
-            const unsigned long long bq = old & kSlotMask;
-            const long long be = (long long)(old >> kSlotBits);
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                if (fr >> r & 1u) {
-                    int v = vv[r];
-                    long long rs = (long long)a.off[v];
-                    a.out[v] = k;
-                    a.Q[bq + pf] = v;
-                    a.QE[bq + pf] = be + pe;
-                    a.QR[bq + pf] = rs;
-                    ++pf;
-                    pe += (long long)a.off[v + 1] - rs;
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-            if (sv >> r & 1u) dst[bs + ps++] = vv[r];
-    }
-    int bm = block_min(lmin, lds);
-    if (threadIdx.x == 0 && bm != INT_MAX) atomicMin(mn_ctr, (unsigned long long)bm);
-}
-
-// One round of level k: this workgroup's slice of the edges of global
-// frontier entries [q0, q1) (edge space [e0, e1)), then everything it asserts
-// on the way, from its LDS queue: small batches expanded here, large ones
-// sent to the global list for the next round.
+// Expand the workgroup's LDS queue until it is empty: a batch of up to 256
+// queued vertices at a time, expanded here when its rows hold at most
+// kLocalMax edges, otherwise sent to the global list for the next round.
 template <typename Off>
-__device__ void po_round(const PoArgs<Off> &a, PoCtx<Off> &c, unsigned long long q0,
-                         unsigned long long q1, unsigned long long e0, unsigned long long e1,
-                         EbLds &E, ExpandLds &X) {
-    edge_balanced(a.Q, a.QE, a.QR, nullptr, nullptr, (long long)q0, (long long)q1, (long long)e0,
-                  (long long)e1, a.cols, E,
-                  [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&)[kEbR], EbLds &) {
-                      relax<Off>(act, u, c);
-                  });
+__device__ void drain_lds(const PoArgs<Off> &a, PoCtx<Off> &c, ExpandLds &X) {
     while (true) {
         __syncthreads();
         const unsigned tk = *c.lq.take, tl = *c.lq.tail;
@@ -320,6 +253,148 @@ __device__ void po_round(const PoArgs<Off> &a, PoCtx<Off> &c, unsigned long long
     }
 }
 
+// First pass over all ids: core = deg, out = 0 for isolated vertices and -1
+// (unclaimed) for the others, which are listed; smallest positive degree.
+template <typename Off>
+__device__ void po_init(const PoArgs<Off> &a, unsigned long long *na_ctr, unsigned long long *mn_ctr,
+                        int *lds, unsigned long long *lds64) {
+    int lmin = INT_MAX;
+    const long long step = (long long)gridDim.x * kTile;
+    for (long long tile = (long long)blockIdx.x * kTile; tile < a.n; tile += step) {
+        unsigned sv = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            long long i = tile + r * kBlock + threadIdx.x;
+            if (i < a.n) {
+                int c = (int)(a.off[i + 1] - a.off[i]);
+                a.core[i] = c;
+                a.out[i] = c == 0 ? 0 : -1;
+                if (c > 0) {
+                    sv |= 1u << r;
+                    lmin = min(lmin, c);
+                }
+            }
+        }
+        int ts = 0;
+        int ps = block_excl_scan(__popc(sv), ts, lds);
+        unsigned long long bs = block_reserve(ts, na_ctr, lds64);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (sv >> r & 1u) a.A0[bs + ps++] = (int)(tile + r * kBlock + threadIdx.x);
+    }
+    int bm = block_min(lmin, lds);
+    if (threadIdx.x == 0 && bm != INT_MAX) atomicMin(mn_ctr, (unsigned long long)bm);
+}
+
+// Scan of the survivor list at level k (Alg. 4, scan kernel), block-
+// aggregated: vertices with core == k are claimed and become frontier,
+// survivors (core > k) go to the next list, and the smallest surviving value
+// is recorded.  A tile's claimed frontier stays in the workgroup's LDS queue
+// while the workgroup's share is small (expanded right after the scan);
+// otherwise it goes to the global list for an edge-balanced round.
+template <typename Off>
+__device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__restrict__ src,
+                        long long nsrc, int32_t *__restrict__ dst, unsigned long long *na_ctr,
+                        unsigned long long *mn_ctr, unsigned long long *nf_ctr, int *lds,
+                        long long *lds_l, unsigned long long *lds64) {
+    GridState *gs = &a.st->g;
+    const int k = c.k;
+    int lmin = INT_MAX;
+    long long local_edges = 0;  // block-uniform
+    int claimed = 0;
+    const long long step = (long long)gridDim.x * kTile;
+    for (long long tile = (long long)blockIdx.x * kTile; tile < nsrc; tile += step) {
+        int vv[8];
+        unsigned fr = 0, sv = 0, cand = 0;
+        long long dsum = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            long long i = tile + r * kBlock + threadIdx.x;
+            int v = -1, cv = -1;
+            if (i < nsrc) {
+                v = src[i];
+                cv = c.core[v];
+            }
+            vv[r] = v;
+            if (cv > k) {
+                sv |= 1u << r;
+                lmin = min(lmin, cv);
+            }
+            if (cv == k) cand |= 1u << r;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            int v = vv[r];
+            if ((cand >> r & 1u) && claim_vertex(c.out, v, k)) {
+                fr |= 1u << r;
+                dsum += (long long)(a.off[v + 1] - a.off[v]);
+            }
+        }
+        int ts = 0;
+        int ps = block_excl_scan(__popc(sv), ts, lds);
+        unsigned long long bs = block_reserve(ts, na_ctr, lds64);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (sv >> r & 1u) dst[bs + ps++] = vv[r];
+        int tf = 0;
+        long long te = 0;
+        int pf = block_excl_scan(__popc(fr), tf, lds);
+        long long pe = block_excl_scan64(dsum, te, lds_l);
+        if (tf == 0) continue;
+        claimed += tf;
+        const unsigned tail = *c.lq.tail, keep = *c.lq.keep;
+        const bool local = local_edges + te <= kLocalMax && tail + tf - keep <= (unsigned)kLq;
+        if (local) {
+            local_edges += te;
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (fr >> r & 1u) c.lq.buf[(tail + pf++) % kLq] = vv[r];
+            __syncthreads();
+            if (threadIdx.x == 0) *c.lq.tail = tail + tf;
+            __syncthreads();
+        } else {
+            if (threadIdx.x == 0)
+                lds64[0] = atomicAdd(&gs->ctr[QET].v,
+                                     ((unsigned long long)te << kSlotBits) | (unsigned long long)tf);
+            __syncthreads();
+            const unsigned long long old = lds64[0];
+            __syncthreads();
+            const unsigned long long bq = old & kSlotMask;
+            const long long be = (long long)(old >> kSlotBits);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if (fr >> r & 1u) {
+                    int v = vv[r];
+                    long long rs = (long long)a.off[v];
+                    a.Q[bq + pf] = v;
+                    a.QE[bq + pf] = be + pe;
+                    a.QR[bq + pf] = rs;
+                    ++pf;
+                    pe += (long long)a.off[v + 1] - rs;
+                }
+            }
+        }
+    }
+    int bm = block_min(lmin, lds);
+    if (threadIdx.x == 0) {
+        if (bm != INT_MAX) atomicMin(mn_ctr, (unsigned long long)bm);
+        if (claimed) atomicAdd(nf_ctr, (unsigned long long)claimed);
+    }
+}
+
+// One edge-balanced round of level k over global frontier entries [q0, q1)
+// (edge space [e0, e1)), then this workgroup's LDS queue.
+template <typename Off>
+__device__ void po_round(const PoArgs<Off> &a, PoCtx<Off> &c, unsigned long long q0,
+                         unsigned long long q1, unsigned long long e0, unsigned long long e1,
+                         EbLds &E, ExpandLds &X) {
+    edge_balanced(a.Q, a.QE, a.QR, nullptr, nullptr, (long long)q0, (long long)q1, (long long)e0,
+                  (long long)e1, a.cols, nullptr, E,
+                  [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&)[kEbR], EbLds &,
+                      const int (&)[kEbR]) { relax<Off>(act, u, c); });
+    drain_lds<Off>(a, c, X);
+}
+
 template <typename Off>
 __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     __shared__ int lds[kWavesPerBlock];
@@ -341,9 +416,9 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
     PhaseClock clk;
     if (timer) clk.start();
-    // Phase 0: core = deg, list of non-isolated vertices, smallest degree.
-    po_scan<Off, true>(a, nullptr, a.n, 0, a.A0, &st->na[0].v, &st->mn[0].v, lds, lds_l, lds64);
-    if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+    // Phase 0: core = deg, claims cleared, list of non-isolated vertices.
+    po_init<Off>(a, &st->na[0].v, &st->mn[0].v, lds, lds64);
+    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[0].v);
     const unsigned long long peelable = ld_rlx(&st->na[0].v);
     long long nprev = (long long)peelable;
@@ -351,7 +426,6 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     unsigned long long q_end = 0, e_end = 0;  // global list consumed so far
     long long levels = 0, scans = 0, rounds = 0;
     int kmax = 0;
-    unsigned long long scanned = 0;  // vertices found by level scans
 
     for (int j = 1; peelable > 0; ++j) {
         const int32_t *src = (j & 1) ? a.A0 : a.A1;
@@ -359,45 +433,56 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st_rlx(&st->na[(j + 1) % 3].v, 0ull);
             st_rlx(&st->mn[(j + 1) % 3].v, (unsigned long long)INT_MAX);
+            st_rlx(&st->nf[(j + 1) % 3].v, 0ull);
         }
-        po_scan<Off, false>(a, src, nprev, c.k, dst, &st->na[j % 3].v, &st->mn[j % 3].v, lds, lds_l,
-                            lds64);
+        po_scan<Off>(a, c, src, nprev, dst, &st->na[j % 3].v, &st->mn[j % 3].v, &st->nf[j % 3].v,
+                     lds, lds_l, lds64);
+        drain_lds<Off>(a, c, xl);
         ++scans;
-        if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
+        const unsigned long long t_scan = wall_clock64();
         if (timer) clk.lap(&st->phase[1].v);
-        unsigned long long q1 = snap[QET] & kSlotMask, e1 = snap[QET] >> kSlotBits;
+        const long long nsurv_in = nprev;
         nprev = (long long)ld_rlx(&st->na[j % 3].v);
-        if (q1 == q_end) {  // empty level: jump to the smallest value left
+        if (ld_rlx(&st->nf[j % 3].v) == 0ull) {  // empty level: jump to the smallest value left
             if (nprev == 0) break;
             c.k = (int)ld_rlx(&st->mn[j % 3].v);
             continue;
         }
-        scanned += q1 - q_end;
         unsigned long long q0 = q_end, e0 = e_end;
+        unsigned long long q1 = snap[QET] & kSlotMask, e1 = snap[QET] >> kSlotBits;
         while (q0 < q1) {
             po_round<Off>(a, c, q0, q1, e0, e1, eb, xl);
             ++rounds;
-            // fold this block's dynamic count in before the barrier's snapshot
-            long long t = wave_sum64(c.ndyn);
-            if (lane_id() == 0 && t) atomicAdd(&gs->ctr[N_DYN].v, (unsigned long long)t);
-            c.ndyn = 0;
-            if (!grid_sync(gs, nb, a.limit, snap, bar)) return;
+            if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
             q0 = q1;
             e0 = e1;
             q1 = snap[QET] & kSlotMask;
             e1 = snap[QET] >> kSlotBits;
         }
         if (timer) clk.lap(&st->phase[2].v);
+        if (timer && a.trace && levels < a.trace_cap) {
+            long long *tr = a.trace + levels * 8;
+            tr[0] = c.k;
+            tr[1] = nsurv_in;
+            tr[2] = (long long)ld_rlx(&st->nf[j % 3].v);
+            tr[3] = (long long)(q1 - q_end);
+            tr[4] = (long long)(e1 - e_end);
+            tr[5] = rounds;
+            tr[6] = (long long)t_scan;
+            tr[7] = (long long)wall_clock64();
+        }
         q_end = q1;
         e_end = e1;
         ++levels;
         kmax = c.k;
-        // every vertex peeled so far was found by a scan or asserted once
-        if (scanned + snap[N_DYN] >= peelable) break;
+        if (nprev == 0) break;  // no survivor left after this level's scan: all claimed
         c.k += 1;
     }
     long long t = wave_sum64(c.natom);
     if (lane_id() == 0 && t) atomicAdd(&gs->ctr[N_ATOM].v, (unsigned long long)t);
+    t = wave_sum64(c.ndyn);
+    if (lane_id() == 0 && t) atomicAdd(&gs->ctr[N_DYN].v, (unsigned long long)t);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->levels.v = (unsigned long long)levels;
         st->scans.v = (unsigned long long)scans;
@@ -439,6 +524,13 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
         return PICO_ENOMEM;
     }
     a.limit = wall_ticks(20.0);
+    a.trace = nullptr;
+    a.trace_cap = 0;
+    const char *trace_file = getenv("PICO_TRACE_FILE");  // development aid
+    if (trace_file && *trace_file) {
+        a.trace_cap = 1 << 14;
+        PICO_HIP_TRY(hipMallocAsync((void **)&a.trace, sizeof(long long) * 8 * a.trace_cap, stream));
+    }
     int blocks = 0;
     int rc = persistent_grid(reinterpret_cast<const void *>(po_persistent<Off>), kBlock,
                              tune_int("PICO_PO_BLOCKS_PER_CU", 1), &blocks);
@@ -455,6 +547,24 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     if (!h) return PICO_EHIP;
     PICO_HIP_TRY(hipMemcpyAsync(h, a.st, sizeof(PoState), hipMemcpyDeviceToHost, stream));
     PICO_HIP_TRY(hipStreamSynchronize(stream));
+    if (a.trace) {
+        const long long nl = (long long)h->levels.v < a.trace_cap ? (long long)h->levels.v : a.trace_cap;
+        std::vector<long long> tr((size_t)nl * 8 + 1);
+        PICO_HIP_TRY(hipMemcpy(tr.data(), a.trace, sizeof(long long) * 8 * nl, hipMemcpyDeviceToHost));
+        PICO_HIP_TRY(hipFree(a.trace));
+        if (FILE *f = fopen(trace_file, "a")) {
+            const double us = 1.0 / (double)wall_ticks(1e-6);
+            fprintf(f, "# level k survivors_in scan_claimed global_entries global_edges rounds_cum "
+                       "rounds_us total_us\n");
+            for (long long i = 0; i < nl; ++i) {
+                const long long *t = &tr[i * 8];
+                double prev_end = i ? (double)tr[(i - 1) * 8 + 7] : (double)t[6];
+                fprintf(f, "%lld %lld %lld %lld %lld %lld %lld %.1f %.1f\n", i, t[0], t[1], t[2], t[3],
+                        t[4], t[5], (t[7] - t[6]) * us, (t[7] - prev_end) * us);
+            }
+            fclose(f);
+        }
+    }
     if (h->g.error.v) {
         set_error("PeelOne kernel stopped (error %llu; grid of %d blocks)",
                   (unsigned long long)h->g.error.v, blocks);

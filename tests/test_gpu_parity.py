@@ -165,3 +165,25 @@ def test_rmat22_full_size(algo):
     got = pico.coreness(g.offsets, g.cols, algo).cpu().numpy()
     want = oracle.bz_coreness(g.offsets.cpu(), g.cols.cpu())
     assert np.array_equal(got, want)
+
+
+def test_rmat26_block_full_size():
+    """The RMAT-26 + planted-block workload at full size (int64 offsets), in the
+    launch configuration bench.py times.  The oracle cannot finish it in test
+    time, so the checks are ones that hold at any size: both algorithms agree
+    bit for bit, 0 <= core <= deg with 0 exactly on isolated vertices, and the
+    h-index fixed point (so every {core >= k} has minimum degree >= k); plus
+    PeelOne's level count equals the number of distinct non-zero values."""
+    import bench
+    g = gg.rmat26_block(device="cuda")
+    print(f"case {g.name} n={g.n} m={g.m}", flush=True)
+    assert g.offsets.dtype == torch.int64
+    po, st_po = pico.coreness(g.offsets, g.cols, "peelone", with_stats=True)
+    hc, st_hc = pico.coreness(g.offsets, g.cols, "histocore", with_stats=True)
+    assert torch.equal(po, hc)
+    props = bench.coreness_properties(g.offsets, g.cols, po)
+    assert all(props.values()), props
+    vals = torch.unique(po)
+    assert st_po["iterations"] == int((vals > 0).sum())
+    assert st_po["k_max"] == int(vals.max())
+    assert st_po["frontier_total"] == int((po > 0).sum())
