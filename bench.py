@@ -115,12 +115,329 @@ def cpu_baseline(g, budget_s: float):
     return core, runs, t_total
 
 
+def _roofline(kname: str, alg_bytes: float, avg_ms: float) -> dict:
+    gbps = alg_bytes / (avg_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(alg_bytes)}
+
+
+def _batch_stats_as_plain(st: dict) -> dict:
+    """The batched kernel's counters under the names algorithmic_bytes reads."""
+    return {"atomics": st["atomics"], "frontier_total": st["frontier_total"],
+            "pushes_dynamic": st["pushes"], "buckets_scanned": st["buckets_scanned"],
+            "edges_scanned": st["edges_scanned"]}
+
+
+def graph_views(batch, torch):
+    """Per graph of a packed batch: (offsets rebased to 0 as int64, cols view,
+    n, m, first global vertex), for plain single-graph calls."""
+    vptr = batch.vptr.cpu()
+    e_at = batch.offsets[batch.vptr].cpu()
+    views = []
+    for g in range(batch.num_graphs):
+        x0, x1 = int(vptr[g]), int(vptr[g + 1])
+        e0, e1 = int(e_at[g]), int(e_at[g + 1])
+        views.append(((batch.offsets[x0:x1 + 1] - e0).contiguous(), batch.cols[e0:e1], x1 - x0,
+                      e1 - e0, x0))
+    torch.cuda.synchronize()
+    return views
+
+
+def oracle_sample(batch, pick, budget_s: float, got=None):
+    """The oracle on graphs of the batch in the order `pick`, until `budget_s`
+    seconds of oracle time: (graphs done, seconds, edges, all equal to `got`)."""
+    import numpy as np
+    import oracle
+    done, t, edges, same = 0, 0.0, 0, True
+    for g in pick:
+        cg = batch.graph(int(g))
+        off = cg.offsets.cpu().numpy().astype(np.int64)
+        cols = cg.cols.cpu().numpy()
+        t0 = time.perf_counter()
+        want = oracle.bz_coreness(off, cols)
+        t += time.perf_counter() - t0
+        done += 1
+        edges += cg.m
+        if got is not None:
+            x0 = int(batch.vptr[int(g)])
+            same = same and bool(np.array_equal(got[x0:x0 + cg.n], want))
+        if t >= budget_s:
+            break
+    return done, t, edges, same
+
+
+def bench_batched(args, pico, torch, np):
+    """4,096 graphs in one batched launch per algorithm, against the plain
+    method called once per graph back to back on the same stream."""
+    import graphgen as gg
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    b = gg.mixed_batch(count=args.graphs, device=dev)
+    torch.cuda.synchronize()
+    G, total_n, total_m = b.num_graphs, b.total_n, b.total_m
+    log(f"batch {b.name}: G={G} total_n={total_n} total_m={total_m} "
+        f"generated in {time.perf_counter() - t0:.1f}s")
+    order = pico.largest_first(b.vptr)
+    algos = args.algos.split(",")
+    views = graph_views(b, torch)
+    ws_plain_bytes = max(pico.pico_workspace_bytes(v[2], v[3], pico.ALGOS[a] | pico.PICO_OFFSETS_I64)
+                         for v in views for a in algos)
+    ws_plain = torch.empty(ws_plain_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    per, outs, kern = {}, {}, {}
+    for a in algos:
+        code = pico.ALGOS[a]
+        tune = None
+        if not args.no_tune:
+            from paper_2402_15253_amd import autotune
+            tune = autotune.tune_batched(b, a, order=order, log=log)
+        wsb = pico.pico_batched_workspace_bytes(G, total_n, total_m, code)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        out_b = torch.empty(total_n, dtype=torch.int32, device=dev)
+        st = pico.BatchStats()
+
+        def one(stats=None):
+            rc = pico.pico_coreness_batched(b.vptr, b.offsets, b.cols, G, total_n, total_m, code, order,
+                                            out_b, tune, ws, wsb, stats, stream)
+            if rc != pico.PICO_OK:
+                raise pico.PicoError(rc, pico.pico_last_error())
+
+        one(st)
+        for _ in range(max(args.warmup - 1, 0)):
+            one()
+        torch.cuda.synchronize()
+        pico.pico_profile_enable(not args.no_profile)
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            one()
+        torch.cuda.synchronize()
+        t_batched = (time.perf_counter() - t_start) / args.steps
+        prof = pico.pico_profile_read() if not args.no_profile else {}
+        pico.pico_profile_enable(False)
+        # the plain method: one call per graph, back to back on the same stream
+        out_p = torch.empty(total_n, dtype=torch.int32, device=dev)
+        pcode = code | pico.PICO_OFFSETS_I64
+
+        def plain_pass():
+            for off, cols, n, m, x0 in views:
+                if n == 0:
+                    continue
+                rc = pico.pico_coreness_ws(off, cols, n, m, pcode, out_p[x0:x0 + n], ws_plain,
+                                           ws_plain_bytes, None, stream)
+                if rc != pico.PICO_OK:
+                    raise pico.PicoError(rc, pico.pico_last_error())
+
+        plain_pass()  # warm-up
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        plain_pass()
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - tp0
+        same = bool(torch.equal(out_b, out_p))
+        sd = st.as_dict()
+        per[a] = {"batched_ms": round(t_batched * 1e3, 3), "plain_ms": round(t_plain * 1e3, 1),
+                  "batched_graphs_per_s": round(G / t_batched, 1),
+                  "plain_graphs_per_s": round(G / t_plain, 1),
+                  "speedup_vs_plain": round(t_plain / t_batched, 2), "identical_to_plain": same,
+                  "batched_gteps": round(total_m / t_batched / 1e9, 3),
+                  "tune": tune.as_dict() if tune else None, "stats": sd}
+        if "batched_kernel" in prof:
+            launches, t_ms = prof["batched_kernel"]
+            avg = t_ms / max(launches, 1)
+            kern[a] = _roofline("batched_kernel", algorithmic_bytes(a, _batch_stats_as_plain(sd),
+                                                                    total_n, total_m, 8), avg)
+        outs[a] = out_b
+        log(f"{a}: {per[a]}")
+        del ws
+    value = len(algos) * G / sum(per[a]["batched_ms"] / 1e3 for a in algos)
+    plain = len(algos) * G / sum(per[a]["plain_ms"] / 1e3 for a in algos)
+    roof = max(kern.values(), key=lambda r: r["avg_launch_ms"]) if kern else None
+    props = {}
+    for a in algos:
+        props[f"{a}==plain"] = per[a]["identical_to_plain"]
+    if len(algos) == 2:
+        props["peelone==histocore"] = bool(torch.equal(outs["peelone"], outs["histocore"]))
+    cpu = None
+    if args.cpu_budget > 0:
+        pick = torch.randperm(G, generator=torch.Generator().manual_seed(5)).tolist()
+        got = next(iter(outs.values())).cpu().numpy()
+        done, t_cpu, edges, same = oracle_sample(b, pick, args.cpu_budget, got)
+        props["sample==oracle"] = same
+        cpu = {"value": round(done / t_cpu, 2), "unit": "graphs/s", "cores": 1, "kind": "oracle",
+               "sample": f"Batagelj-Zaversnik peel, single thread, {done} graphs of the batch in a "
+                         f"seeded random order ({edges} directed edges, {t_cpu:.1f}s); host "
+                         f"nproc={os.cpu_count()}"}
+    ok = all(props.values())
+    if not ok:
+        log(f"PARITY FAILURE: {props}")
+    rec = {
+        "metric": "batched graphs/s (one launch per algorithm) vs sequential plain launches",
+        "value": round(value, 1), "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sum(per[a]["batched_ms"] for a in algos), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{G} graphs, vertex counts log-uniform in [200, 200000], even ones "
+                               "Erdos-Renyi G(n, M) avg degree U(4,32), odd ones R-MAT edge factor "
+                               "U(8,16); packed multi-CSR, int64 offsets, int32 graph-local cols; "
+                               "seed 4096",
+                   "graphs": G, "total_n": total_n, "total_m": total_m,
+                   "step": " + ".join(f"batched {a}" for a in algos), "parallelism": "single GPU"},
+        "plain_graphs_per_s": round(plain, 1), "vs_plain": round(value / plain, 2),
+        "roofline": roof, "cpu_baseline": cpu, "per_algo": per,
+        "parity": "identical to plain calls" + (" and oracle sample" if cpu else "") if ok else props,
+    }
+    print(json.dumps(rec), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
+def bench_serving(args, pico, torch, np):
+    """A Poisson stream of requests served by the continuous-batching server,
+    then the same trace through a serial loop of plain calls."""
+    import graphgen as gg
+    dev = "cuda:0"
+    algo = args.algos.split(",")[0]
+    code = pico.ALGOS[algo]
+    t0 = time.perf_counter()
+    pool = gg.serving_pool(count=args.pool, device=dev)
+    torch.cuda.synchronize()
+    log(f"pool {pool.name}: total_n={pool.total_n} total_m={pool.total_m} "
+        f"in {time.perf_counter() - t0:.1f}s")
+    arrivals, pick = gg.poisson_trace(args.rate, args.duration, pool.num_graphs)
+    R = arrivals.numel()
+    views = graph_views(pool, torch)
+    # each pool graph alone (the plain single-graph call): the reference
+    ws_bytes = max(pico.pico_workspace_bytes(v[2], v[3], code | pico.PICO_OFFSETS_I64) for v in views)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ref = torch.empty(pool.total_n, dtype=torch.int32, device=dev)
+    plain_ms = []
+    for off, cols, n, m, x0 in views:
+        st = pico.PicoStats()
+        rc = pico.pico_coreness_ws(off, cols, n, m, code | pico.PICO_OFFSETS_I64, ref[x0:x0 + n], ws,
+                                   ws_bytes, st, None)
+        if rc != pico.PICO_OK:
+            raise pico.PicoError(rc, pico.pico_last_error())
+        plain_ms.append(st.elapsed_ms)
+    vp = pool.vptr.cpu().numpy()
+    ep = pool.offsets[pool.vptr].cpu().numpy()
+    sizes = vp[1:] - vp[:-1]
+    medges = ep[1:] - ep[:-1]
+    req_n = sizes[pick.numpy()]
+    base = np.concatenate([[0], np.cumsum(req_n)])
+    out = torch.empty(int(base[-1]) + 1, dtype=torch.int32, device=dev)
+    off_ptr = [pool.offsets.data_ptr() + 8 * int(vp[g]) for g in range(pool.num_graphs)]
+    cols_ptr = pool.cols.data_ptr()
+    out_ptr = out.data_ptr()
+    free = torch.cuda.mem_get_info()[0]
+    arena = int(min(args.arena_gb * 1e9, free - (8 << 30))) & ~255
+    log(f"requests {R} over {args.duration}s; arena {arena / 1e9:.1f} GB; "
+        f"pool graph sizes p50 {np.median(sizes):.0f} p99 {np.percentile(sizes, 99):.0f}")
+    tune = None
+    if not args.no_tune:
+        from paper_2402_15253_amd import autotune
+        tune = autotune.tune_batched(pool, algo, order=pico.largest_first(pool.vptr), log=log)
+    srv = pico.Server(algo, arena_bytes=arena, max_inflight=args.inflight,
+                      max_tasks_per_launch=4096, tune=tune)
+    torch.cuda.synchronize()
+    arr = arrivals.numpy()
+    pk = pick.numpy()
+    t_done = np.zeros(R)
+    t_start = time.perf_counter_ns()
+    i = done = 0
+    last_log = time.perf_counter()
+    while done < R:
+        now = (time.perf_counter_ns() - t_start) / 1e9
+        while i < R and arr[i] <= now:
+            g = int(pk[i])
+            srv.submit_ptrs(off_ptr[g], cols_ptr, int(sizes[g]), int(medges[g]),
+                            out_ptr + 4 * int(base[i]), i)
+            i += 1
+        k, buf = srv.progress_raw()
+        if k:
+            seen = (time.perf_counter_ns() - t_start) / 1e9  # result ready, as the client sees it
+            for j in range(k):
+                t_done[buf[j].tag] = seen
+        done += k
+        if time.perf_counter() - last_log > 10:
+            last_log = time.perf_counter()
+            log(f"  t={now:.1f}s submitted {i} done {done} {srv.status()}")
+    st = srv.status()
+    srv.close()
+    elapsed = t_done.max()
+    lat = (t_done - arr) * 1e3
+    served = {"graphs_per_s": round(R / elapsed, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+              "p99_ms": round(float(np.percentile(lat, 99)), 3),
+              "max_ms": round(float(lat.max()), 3), "launches": st["launches"],
+              "requests": R, "elapsed_s": round(float(elapsed), 3)}
+    log(f"server: {served}")
+    # every request's result equals its graph's result alone
+    same = True
+    for r in range(R):
+        g = int(pk[r])
+        if not torch.equal(out[base[r]:base[r + 1]], ref[vp[g]:vp[g + 1]]):
+            same = False
+            log(f"request {r} (graph {g}) differs from the graph alone")
+            break
+    # the serial plain loop on the same trace (capped in wall time)
+    ws_stream = torch.cuda.current_stream()
+    done_p = np.full(R, np.nan)
+    t_start = time.perf_counter()
+    for r in range(R):
+        now = time.perf_counter() - t_start
+        if now > args.plain_budget:
+            break
+        if arr[r] > now:
+            time.sleep(arr[r] - now)
+        off, cols, n, m, x0 = views[int(pk[r])]
+        rc = pico.pico_coreness_ws(off, cols, n, m, code | pico.PICO_OFFSETS_I64,
+                                   out[base[r]:base[r] + n], ws, ws_bytes, None, ws_stream)
+        if rc != pico.PICO_OK:
+            raise pico.PicoError(rc, pico.pico_last_error())
+        done_p[r] = time.perf_counter() - t_start
+    fin = ~np.isnan(done_p)
+    lat_p = (done_p[fin] - arr[fin]) * 1e3
+    plain = {"graphs_per_s": round(float(fin.sum() / np.nanmax(done_p)), 1),
+             "p50_ms": round(float(np.percentile(lat_p, 50)), 3),
+             "p99_ms": round(float(np.percentile(lat_p, 99)), 3),
+             "completed": int(fin.sum()), "of": R,
+             "note": "stopped at the wall-clock cap" if fin.sum() < R else "whole trace"}
+    log(f"plain loop: {plain}")
+    cpu = None
+    if args.cpu_budget > 0:
+        done_c, t_cpu, edges, _ = oracle_sample(pool, pk.tolist(), args.cpu_budget)
+        cpu = {"value": round(done_c / t_cpu, 2), "unit": "graphs/s", "cores": 1, "kind": "oracle",
+               "sample": f"Batagelj-Zaversnik peel, single thread, the first {done_c} requests' "
+                         f"graphs ({edges} directed edges, {t_cpu:.1f}s); host nproc={os.cpu_count()}"}
+    rec = {
+        "metric": "served graphs/s with p50/p99 latency (arrival to result) vs a serial plain loop",
+        "value": served["graphs_per_s"], "unit": "graphs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(float(elapsed) * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals {args.rate:g}/s for {args.duration:g}s, graphs "
+                               f"from a pool of {pool.num_graphs} R-MAT (edge factor 16) graphs with "
+                               "lognormal vertex counts (median 20000, sigma 1.5, cap 8M); seeds 2000",
+                   "algo": algo, "requests": R, "arena_bytes": arena,
+                   "inflight_slots": args.inflight, "parallelism": "single GPU"},
+        "latency_ms": {"p50": served["p50_ms"], "p99": served["p99_ms"], "max": served["max_ms"]},
+        "served": served, "plain_loop": plain,
+        "vs_plain": round(served["graphs_per_s"] / max(plain["graphs_per_s"], 1e-9), 2),
+        "roofline": None, "cpu_baseline": cpu,
+        "parity": "every request identical to its graph alone" if same else "MISMATCH",
+        "pool_plain_ms_mean": round(float(np.mean(plain_ms)), 3),
+    }
+    print(json.dumps(rec), flush=True)
+    if not same:
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="rmat22", choices=["er10k", "rmat22", "rmat26"])
+    ap.add_argument("--config", default="rmat22",
+                    choices=["er10k", "rmat22", "rmat26", "batched", "serving"])
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--algos", default="peelone,histocore",
@@ -129,6 +446,17 @@ def main():
                     help="after timing, copy 1 GiB device to device (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not bracket kernels with HIP events during the timed steps")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched: skip the autotuner and use the default launch parameters")
+    ap.add_argument("--graphs", type=int, default=4096, help="batched: number of graphs")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serving: trace length (s)")
+    ap.add_argument("--pool", type=int, default=2048, help="serving: graphs in the request pool")
+    ap.add_argument("--arena-gb", type=float, default=200.0,
+                    help="serving: HBM admission budget for request state (GB)")
+    ap.add_argument("--inflight", type=int, default=4, help="serving: launch slots")
+    ap.add_argument("--plain-budget", type=float, default=60.0,
+                    help="serving: wall-clock cap (s) on the serial plain-loop baseline")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -144,6 +472,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.config == "batched":
+        return bench_batched(args, pico, torch, np)
+    if args.config == "serving":
+        return bench_serving(args, pico, torch, np)
     t0 = time.perf_counter()
     g, desc = make_graph(args.config, dev)
     torch.cuda.synchronize()

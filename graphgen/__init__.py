@@ -117,22 +117,50 @@ class CSRGraph:
         return src, self.cols.to(torch.int64)
 
 
+# torch.unique and boolean selection run on device libraries that index with
+# 32-bit counts, so no single call may see 2**31 or more elements.
+_PIECE_MAX = 1 << 30
+
+
+def _unique_pieces(parts, lo: int, hi: int) -> list:
+    """Sorted distinct values of the union of ``parts`` (all in [lo, hi)), as
+    a list of ascending pieces covering consecutive value ranges."""
+    total = sum(int(p.numel()) for p in parts)
+    if total <= _PIECE_MAX or hi - lo <= 1:
+        return [torch.unique(torch.cat(parts) if len(parts) > 1 else parts[0])]
+    mid = lo + (hi - lo) // 2
+    left = [p[p < mid] for p in parts]
+    right = [p[p >= mid] for p in parts]
+    del parts
+    return _unique_pieces(left, lo, mid) + _unique_pieces(right, mid, hi)
+
+
 def csr_from_pairs(n: int, src: torch.Tensor, dst: torch.Tensor, *,
                    offsets_dtype: torch.dtype = torch.int32, name: str = "graph",
                    meta: dict | None = None) -> CSRGraph:
     """Symmetrise, drop self-loops and duplicates, and sort into CSR."""
-    src = src.to(torch.int64)
-    dst = dst.to(torch.int64)
-    keep = src != dst
-    src, dst = src[keep], dst[keep]
-    key = torch.cat([src * n + dst, dst * n + src])
-    del src, dst, keep
-    key = torch.unique(key)  # sorted ascending: row-major CSR order
-    rows = torch.div(key, n, rounding_mode="floor")
-    cols = (key - rows * n).to(torch.int32)
-    del key
-    counts = torch.bincount(rows, minlength=n)
-    del rows
+    parts = []
+    for c0 in range(0, src.numel(), _PIECE_MAX):
+        s = src[c0:c0 + _PIECE_MAX].to(torch.int64)
+        d = dst[c0:c0 + _PIECE_MAX].to(torch.int64)
+        keep = s != d
+        s, d = s[keep], d[keep]
+        parts += [s * n + d, d * n + s]
+        del s, d, keep
+    if not parts:
+        parts = [torch.zeros(0, dtype=torch.int64, device=src.device)]
+    # distinct keys, ascending: row-major CSR order
+    pieces = _unique_pieces(parts, 0, max(n * n, 1))
+    del parts
+    counts = torch.zeros(n, dtype=torch.int64, device=pieces[0].device)
+    cols = []
+    for k in pieces:
+        rows = torch.div(k, n, rounding_mode="floor")
+        counts += torch.bincount(rows, minlength=n)
+        cols.append((k - rows * n).to(torch.int32))
+        del rows
+    del pieces
+    cols = torch.cat(cols) if len(cols) > 1 else cols[0]
     m = int(cols.numel())
     if offsets_dtype == torch.int32 and m >= 2**31:
         raise ValueError("graph too large for int32 offsets")
@@ -423,3 +451,178 @@ def log_uniform_int(seed: int, idx: torch.Tensor, lo: int, hi: int) -> torch.Ten
     """Integers log-uniform on [lo, hi] (exp of a 32-bit uniform, float64)."""
     u = uniform_u32(seed, idx).to(torch.float64) / 2**32
     return torch.floor(torch.exp(math.log(lo) + u * (math.log(hi + 1) - math.log(lo)))).to(torch.int64).clamp(lo, hi)
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent graphs (packed multi-CSR)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class GraphBatch:
+    """Many graphs in one packed CSR: graph g owns global vertices
+    [vptr[g], vptr[g+1]); offsets are global int64 positions into cols; cols
+    hold graph-local neighbour ids."""
+
+    name: str
+    vptr: torch.Tensor     # int64 [G + 1]
+    offsets: torch.Tensor  # int64 [total_n + 1]
+    cols: torch.Tensor     # int32 [total_m]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def num_graphs(self) -> int:
+        return self.vptr.numel() - 1
+
+    @property
+    def total_n(self) -> int:
+        return int(self.vptr[-1])
+
+    @property
+    def total_m(self) -> int:
+        return int(self.cols.numel())
+
+    def to(self, device) -> "GraphBatch":
+        return GraphBatch(self.name, self.vptr.to(device), self.offsets.to(device),
+                          self.cols.to(device), dict(self.meta))
+
+    def graph(self, g: int) -> CSRGraph:
+        """Graph g on its own, with int32 or int64 offsets as it needs."""
+        x0, x1 = int(self.vptr[g]), int(self.vptr[g + 1])
+        off = self.offsets[x0:x1 + 1].to(torch.int64)
+        e0 = int(off[0])
+        off = off - e0
+        m = int(off[-1])
+        cols = self.cols[e0:e0 + m]
+        dt = torch.int32 if m < 2**31 else torch.int64
+        return CSRGraph(f"{self.name}[{g}]", x1 - x0, m, off.to(dt), cols, {})
+
+
+def pack_pairs(sizes: torch.Tensor, gsrc: torch.Tensor, gdst: torch.Tensor, name: str,
+               meta: dict | None = None) -> GraphBatch:
+    """Packed multi-CSR of disjoint graphs from global endpoint pairs (graph g's
+    local vertex v is global id vptr[g] + v): symmetrised, deduplicated,
+    self-loops removed."""
+    sizes = sizes.to(torch.int64)
+    vptr = torch.zeros(sizes.numel() + 1, dtype=torch.int64, device=sizes.device)
+    vptr[1:] = torch.cumsum(sizes, 0)
+    total = int(vptr[-1])
+    g = csr_from_pairs(total, gsrc, gdst, offsets_dtype=torch.int64, name=name)
+    # global -> graph-local column ids, in pieces of the position range
+    dv = g.cols.device
+    vp = vptr.to(dv)
+    cols = g.cols
+    for c0 in range(0, g.m, _PIECE_MAX):
+        c1 = min(g.m, c0 + _PIECE_MAX)
+        pos = torch.arange(c0, c1, device=dv)
+        row = torch.searchsorted(g.offsets, pos, right=True) - 1
+        graph = torch.searchsorted(vp, row, right=True) - 1
+        cols[c0:c1] -= vp[graph].to(torch.int32)
+        del pos, row, graph
+    return GraphBatch(name, vp, g.offsets, cols, meta or {})
+
+
+def batch_sizes(count: int, lo: int, hi: int, seed: int) -> torch.Tensor:
+    """Vertex counts log-uniform on [lo, hi] (computed on the CPU, so identical
+    on every device)."""
+    return log_uniform_int(stream_seed(seed, 0x51), torch.arange(count), lo, hi)
+
+
+_RMAT_THR = (int(round(0.57 * 2**32)), int(round(0.76 * 2**32)), int(round(0.95 * 2**32)))
+
+
+def _rmat_local_pairs(n: int, ef: int, gs: int, device):
+    """ef * n R-MAT endpoint pairs over [0, n) (scale ceil(log2 n), endpoints
+    >= n redrawn, (0.57, 0.19, 0.19)), relabelled by a seeded bijection."""
+    scale = max(1, (n - 1).bit_length())
+    e = torch.arange(ef * n, dtype=torch.int64, device=device)
+    s, t = _rmat_endpoints(e, scale, gs, _RMAT_THR)
+    for attempt in range(1, 257):
+        bad = (s >= n) | (t >= n)
+        if not bool(bad.any()):
+            break
+        rs, rd = _rmat_endpoints(e[bad] + attempt * (1 << 40), scale, gs, _RMAT_THR)
+        s[bad], t[bad] = rs, rd
+    keep = (s < n) & (t < n)
+    s, t = s[keep], t[keep]
+    p = stream_seed(gs, 0x50)
+    return _permute_n(s, n, p), _permute_n(t, n, p)
+
+
+def mixed_batch(count: int = 4096, lo: int = 200, hi: int = 200_000, seed: int = 4096,
+                device="cpu") -> GraphBatch:
+    """The batched workload: `count` graphs with vertex counts log-uniform on
+    [lo, hi]; even-indexed graphs Erdos-Renyi G(n, M) with average degree
+    uniform on [4, 32], odd-indexed R-MAT (scale ceil(log2 n), endpoints >= n
+    redrawn) with edge factor uniform on [8, 16] and (0.57, 0.19, 0.19).
+    Graph g draws from streams seeded by (seed, g)."""
+    sizes = batch_sizes(count, lo, hi, seed)
+    u = uniform_u32(stream_seed(seed, 0x52), torch.arange(count)).to(torch.float64) / 2**32
+    srcs, dsts = [], []
+    vbase = 0
+    for g in range(count):
+        n = int(sizes[g])
+        gs = stream_seed(seed, g)
+        if g % 2 == 0:
+            d = 4.0 + 28.0 * float(u[g])
+            M = int(round(d * n / 2))
+            e = torch.arange(M, dtype=torch.int64, device=device)
+            s = _lsr(rand64(gs, 2 * e), 1) % n
+            t = _lsr(rand64(gs, 2 * e + 1), 1) % n
+        else:
+            ef = min(8 + int(float(u[g]) * 9), 16)
+            s, t = _rmat_local_pairs(n, ef, gs, device)
+        srcs.append(s + vbase)
+        dsts.append(t + vbase)
+        vbase += n
+    return pack_pairs(sizes.to(device), torch.cat(srcs), torch.cat(dsts),
+                      name=f"batch(count={count},n=[{lo},{hi}],seed={seed})",
+                      meta={"count": count, "lo": lo, "hi": hi, "seed": seed})
+
+
+# ---------------------------------------------------------------------------
+# Serving workload: a pool of request graphs and a Poisson arrival trace
+# ---------------------------------------------------------------------------
+
+def std_normal(seed: int, idx: torch.Tensor) -> torch.Tensor:
+    """Standard normal deviates (Box-Muller on two counter-based uniforms)."""
+    u1 = (uniform_u32(seed, 2 * idx).to(torch.float64) + 0.5) / 2**32
+    u2 = (uniform_u32(seed, 2 * idx + 1).to(torch.float64) + 0.5) / 2**32
+    return torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * math.pi * u2)
+
+
+def lognormal_sizes(count: int, median: int, sigma: float, cap: int, seed: int,
+                    lo: int = 2) -> torch.Tensor:
+    """Vertex counts floor(median * exp(sigma * z)), clamped to [lo, cap]."""
+    z = std_normal(stream_seed(seed, 0x4C), torch.arange(count))
+    return torch.floor(median * torch.exp(sigma * z)).to(torch.int64).clamp(lo, cap)
+
+
+def serving_pool(count: int = 2048, median: int = 20_000, sigma: float = 1.5, cap: int = 8_000_000,
+                 edge_factor: int = 16, seed: int = 2000, device="cpu") -> GraphBatch:
+    """The pool the serving trace draws from: `count` R-MAT graphs (edge factor
+    16, (0.57, 0.19, 0.19)) with lognormal vertex counts (median 20,000,
+    sigma 1.5, capped at 8,000,000), packed like a batch."""
+    sizes = lognormal_sizes(count, median, sigma, cap, seed)
+    srcs, dsts, vbase = [], [], 0
+    for g in range(count):
+        n = int(sizes[g])
+        s, t = _rmat_local_pairs(n, edge_factor, stream_seed(seed, 0x10000 + g), device)
+        srcs.append(s + vbase)
+        dsts.append(t + vbase)
+        vbase += n
+    return pack_pairs(sizes.to(device), torch.cat(srcs), torch.cat(dsts),
+                      name=f"serving-pool(count={count},median={median},sigma={sigma},seed={seed})",
+                      meta={"count": count, "median": median, "sigma": sigma, "cap": cap,
+                            "edge_factor": edge_factor, "seed": seed})
+
+
+def poisson_trace(rate: float, duration: float, pool_size: int, seed: int = 2000):
+    """Arrival times (seconds, float64, increasing) of a Poisson stream at
+    `rate` per second over `duration` seconds, and the pool graph each
+    request asks for (uniform over the pool).  CPU tensors."""
+    est = int(rate * duration * 1.2 + 64)
+    u = (uniform_u32(stream_seed(seed, 0x41), torch.arange(est)).to(torch.float64) + 0.5) / 2**32
+    t = torch.cumsum(-torch.log(u) / rate, 0)
+    t = t[t < duration]
+    pick = uniform_u32(stream_seed(seed, 0x42), torch.arange(t.numel())) % pool_size
+    return t, pick.to(torch.int64)

@@ -130,6 +130,182 @@ PICO_API int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, 
                      int algo, int32_t *out_core, void *workspace, size_t ws_bytes,
                      pico_stats *stats, void *stream);
 
+/* Tuning of the batched kernel (NULL = defaults). */
+typedef struct pico_batch_tune {
+    int32_t lds_bytes;      /* dynamic LDS per workgroup for a graph's vertex values;
+                               graphs with more than lds_bytes / 4 vertices keep them
+                               in global memory.  -1 = default (64 KiB), clamped to the
+                               device limit. */
+    int32_t blocks_per_cu;  /* resident workgroups per compute unit; 0 = occupancy limit
+                               (larger values are clamped to it) */
+    int32_t sum_wave_min;   /* HistoCore SumHisto: a vertex whose value exceeds this
+                               scans its buckets with a whole wave, smaller ones with
+                               one thread; 0 = default (64) */
+    int32_t reserved;       /* must be 0 */
+} pico_batch_tune;
+
+/* Statistics of one batched call (filled only if requested; the call then
+   waits for the device). */
+typedef struct pico_batch_stats {
+    int64_t graphs;
+    int64_t iterations;      /* PeelOne: non-empty levels summed over graphs;
+                                HistoCore: rounds summed over graphs */
+    int64_t atomics;         /* PeelOne: decrements; HistoCore: histogram moves
+                                (two atomic RMWs each); summed over graphs */
+    int64_t frontier_total;  /* PeelOne: vertices peeled; HistoCore: sum over
+                                rounds of the frontier size */
+    int64_t edges_scanned;   /* adjacency entries read by the frontier phases
+                                (PeelOne drain, HistoCore UpdateHisto) */
+    int64_t buckets_scanned; /* HistoCore: histogram buckets read by SumHisto */
+    int64_t pushes;          /* PeelOne: vertices asserted during a level's drain;
+                                HistoCore: next-frontier pushes by UpdateHisto */
+    int64_t lds_graphs;      /* graphs whose vertex values lived in LDS */
+    int64_t workgroups;      /* workgroups launched */
+    int32_t lds_bytes;       /* dynamic LDS per workgroup used */
+    int32_t blocks_per_cu;   /* resident workgroups per compute unit used */
+} pico_batch_stats;
+
+/*
+ * pico_batched_workspace_bytes -- device scratch for pico_coreness_batched
+ * over num_graphs graphs totalling total_n vertices and total_m directed
+ * entries.
+ */
+PICO_API int pico_batched_workspace_bytes(int64_t num_graphs, int64_t total_n, int64_t total_m,
+                                          int algo, size_t *bytes);
+
+/*
+ * pico_coreness_batched -- coreness of many independent graphs in one launch
+ * (each graph decomposed by Alg. 4 or Alg. 6 of the paper inside one
+ * workgroup).  Packed multi-CSR, all device pointers:
+ *   graph_vptr   int64[num_graphs + 1]: graph g owns global vertices
+ *                [graph_vptr[g], graph_vptr[g+1]); graph_vptr[num_graphs] = total_n
+ *   csr_offsets  int64[total_n + 1]: row of global vertex x is
+ *                csr_cols[csr_offsets[x] .. csr_offsets[x+1]); csr_offsets[0] = 0,
+ *                csr_offsets[total_n] = total_m
+ *   csr_cols     int32[total_m]: graph-local neighbour ids in [0, n_g)
+ *   order        int32[num_graphs] processing order (e.g. largest graph first),
+ *                or NULL for 0..num_graphs-1
+ *   out_core     int32[total_n], caller-owned
+ * `algo` is PICO_ALGO_PEELONE or PICO_ALGO_HISTOCORE (offsets are always
+ * int64 here; PICO_OFFSETS_I64 is accepted and ignored).  Each graph must be
+ * a simple undirected graph with fewer than 2^31 vertices and edges.  The
+ * workspace (>= pico_batched_workspace_bytes, 256-byte aligned) is
+ * caller-owned.  The call only enqueues work on `stream` unless `stats` is
+ * non-NULL, in which case it waits and fills it; out_core is valid once the
+ * stream has completed.
+ */
+PICO_API int pico_coreness_batched(const int64_t *graph_vptr, const int64_t *csr_offsets,
+                                   const int32_t *csr_cols, int64_t num_graphs, int64_t total_n,
+                                   int64_t total_m, int algo, const int32_t *order,
+                                   int32_t *out_core, const pico_batch_tune *tune, void *workspace,
+                                   size_t ws_bytes, pico_batch_stats *stats, void *stream);
+
+/*
+ * Task lists: the batched kernel over graphs that live anywhere in device
+ * memory, each with its own output and scratch (the form a request server
+ * needs).  One descriptor per graph:
+ *   offsets   device int64[n+1]: positions into cols; offsets[0] need not be 0
+ *   cols      device int32: the graph's rows at cols[offsets[v] .. offsets[v+1]),
+ *             graph-local neighbour ids in [0, n)
+ *   n, m      vertices (< 2^31) and directed entries (offsets[n] - offsets[0])
+ *   out_core  device int32[n], caller-owned
+ *   scratch   device, 256-byte aligned, scratch_bytes >= pico_task_scratch_bytes
+ *             (n, m, algo), caller-owned; its contents are clobbered
+ * Scratch of concurrently running tasks must not overlap.
+ */
+typedef struct pico_task {
+    const int64_t *offsets;
+    const int32_t *cols;
+    int64_t n;
+    int64_t m;
+    int32_t *out_core;
+    void *scratch;
+    size_t scratch_bytes;
+} pico_task;
+
+/* pico_task_scratch_bytes -- per-task scratch for a graph of n vertices and m
+   directed entries: 16 n bytes for PeelOne, 20 n + 4 m for HistoCore (each
+   array rounded up to 256 bytes). */
+PICO_API int pico_task_scratch_bytes(int64_t n, int64_t m, int algo, size_t *bytes);
+
+/* pico_tasks_workspace_bytes -- device workspace of pico_coreness_tasks for a
+   list of num_tasks descriptors (task tables and counters). */
+PICO_API int pico_tasks_workspace_bytes(int64_t num_tasks, size_t *bytes);
+
+/*
+ * pico_coreness_tasks -- coreness of every graph of a task list in one launch
+ * of the batched kernel (each graph by Alg. 4 or Alg. 6 inside one workgroup;
+ * tasks are claimed in list order, so put large graphs first).  `tasks` is a
+ * HOST array, copied to the workspace on `stream` during the call and free to
+ * reuse on return.  Arguments are checked on the host: n in [0, 2^31), m >= 0,
+ * pointers present, scratch large enough and aligned (PICO_EINVAL /
+ * PICO_ENOMEM).  Enqueues only, unless `stats` is non-NULL (then waits).
+ */
+PICO_API int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int algo,
+                                 const pico_batch_tune *tune, void *workspace, size_t ws_bytes,
+                                 pico_batch_stats *stats, void *stream);
+
+/*
+ * Request server: continuous batching of decomposition requests on one GPU.
+ * Requests name a device-resident graph (int64 offsets, as in pico_task) and
+ * a device output.  A request is admitted once its scratch
+ * (pico_task_scratch_bytes) fits in the caller's HBM arena; admitted requests
+ * are launched together, largest first, as one batched-kernel call on a free
+ * launch slot (one HIP stream each, up to max_inflight in flight), so
+ * requests that arrive while others run start on a free slot at once and
+ * overlap with them on the device.  Admission is first come, first served.
+ * The caller drives it: submit queues, progress reaps finished launches,
+ * launches what fits and returns completions.  Single host thread per server.
+ */
+typedef struct pico_server pico_server;
+
+typedef struct pico_server_config {
+    int32_t algo;                  /* PICO_ALGO_PEELONE or PICO_ALGO_HISTOCORE */
+    int32_t max_inflight;          /* launch slots (streams), 1..64 */
+    int64_t max_tasks_per_launch;  /* requests per launch, >= 1 */
+    void *arena;                   /* device, 256-byte aligned, caller-owned: the
+                                      admission budget for request scratch */
+    size_t arena_bytes;
+    pico_batch_tune tune;          /* batched-kernel tuning (zeros / -1 = defaults) */
+} pico_server_config;
+
+typedef struct pico_request {
+    const int64_t *offsets;  /* device int64[n+1], positions into cols */
+    const int32_t *cols;     /* device int32, graph-local ids */
+    int64_t n, m;
+    int32_t *out_core;       /* device int32[n], caller-owned, valid on completion */
+    int64_t tag;             /* caller's id, returned in the completion */
+} pico_request;
+
+typedef struct pico_completion {
+    int64_t tag;
+    int32_t status;          /* PICO_OK */
+    int32_t reserved;
+    uint64_t t_submit_ns;    /* host steady-clock times: submit, launch, and */
+    uint64_t t_launch_ns;    /* when progress saw the launch complete */
+    uint64_t t_done_ns;
+} pico_completion;
+
+typedef struct pico_server_status {
+    int64_t waiting, inflight, ready, busy_slots, launches, completed, arena_used, arena_bytes;
+} pico_server_status;
+
+/* pico_server_create -- set up streams, events, pinned staging and per-slot
+   device tables; the arena stays caller-owned and must outlive the server. */
+PICO_API int pico_server_create(const pico_server_config *cfg, pico_server **server);
+/* pico_server_submit -- queue one request (host-checked; PICO_ENOMEM if its
+   scratch can never fit the arena).  Does not touch the device. */
+PICO_API int pico_server_submit(pico_server *server, const pico_request *req);
+/* pico_server_progress -- reap, launch, and copy up to max_done completions
+   into done (host array); *num_done gets the count.  Never blocks. */
+PICO_API int pico_server_progress(pico_server *server, pico_completion *done, int max_done,
+                                  int *num_done);
+/* pico_server_query -- queue lengths, launches so far and arena use. */
+PICO_API int pico_server_query(const pico_server *server, pico_server_status *status);
+/* pico_server_destroy -- wait for launches in flight, release everything the
+   server allocated; requests still waiting are dropped. */
+PICO_API int pico_server_destroy(pico_server *server);
+
 /*
  * pico_validate_csr -- O(n + m) device check of the preconditions that are
  * cheap to verify in place: offsets[0] == 0, offsets[n] == m, offsets

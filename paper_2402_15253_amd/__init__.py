@@ -23,6 +23,11 @@ __all__ = [
     "pico_coreness", "pico_coreness_ws", "pico_workspace_bytes", "pico_validate_csr",
     "pico_status_string", "pico_last_error", "pico_version", "coreness", "library_path",
     "load_library", "EXPORTED_SYMBOLS", "pico_profile_enable", "pico_profile_read",
+    "pico_batched_workspace_bytes", "pico_coreness_batched", "coreness_batched", "BatchTune",
+    "BatchStats", "largest_first", "Task", "ServerConfig", "Request", "Completion",
+    "ServerStatus", "pico_task_scratch_bytes", "pico_tasks_workspace_bytes", "pico_coreness_tasks",
+    "Server", "pico_server_create", "pico_server_submit", "pico_server_progress",
+    "pico_server_query", "pico_server_destroy",
 ]
 
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
@@ -31,7 +36,11 @@ ALGOS = {"peelone": PICO_ALGO_PEELONE, "histocore": PICO_ALGO_HISTOCORE}
 
 EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_workspace_bytes",
                     "pico_validate_csr", "pico_status_string", "pico_last_error", "pico_version",
-                    "pico_profile_enable", "pico_profile_read")
+                    "pico_profile_enable", "pico_profile_read", "pico_batched_workspace_bytes",
+                    "pico_coreness_batched", "pico_task_scratch_bytes",
+                    "pico_tasks_workspace_bytes", "pico_coreness_tasks", "pico_server_create",
+                    "pico_server_submit", "pico_server_progress", "pico_server_query",
+                    "pico_server_destroy")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpico.so")
@@ -56,6 +65,67 @@ class PicoStats(ctypes.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("reserved", "phase_ms")}
         d["phase_ms"] = [round(x, 4) for x in self.phase_ms]
         return d
+
+
+class BatchTune(ctypes.Structure):
+    _fields_ = [("lds_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("sum_wave_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def __init__(self, lds_bytes: int = -1, blocks_per_cu: int = 0, sum_wave_min: int = 0):
+        super().__init__(lds_bytes, blocks_per_cu, sum_wave_min, 0)
+
+    def as_dict(self) -> dict:
+        return {"lds_bytes": self.lds_bytes, "blocks_per_cu": self.blocks_per_cu,
+                "sum_wave_min": self.sum_wave_min}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("graphs", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("atomics", ctypes.c_int64), ("frontier_total", ctypes.c_int64),
+                ("edges_scanned", ctypes.c_int64), ("buckets_scanned", ctypes.c_int64),
+                ("pushes", ctypes.c_int64), ("lds_graphs", ctypes.c_int64),
+                ("workgroups", ctypes.c_int64), ("lds_bytes", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Task(ctypes.Structure):
+    """C ``pico_task``: one graph of a task list."""
+    _fields_ = [("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("out_core", ctypes.c_void_p), ("scratch", ctypes.c_void_p),
+                ("scratch_bytes", ctypes.c_size_t)]
+
+
+class ServerConfig(ctypes.Structure):
+    """C ``pico_server_config``."""
+    _fields_ = [("algo", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_tasks_per_launch", ctypes.c_int64), ("arena", ctypes.c_void_p),
+                ("arena_bytes", ctypes.c_size_t), ("tune", BatchTune)]
+
+
+class Request(ctypes.Structure):
+    """C ``pico_request``."""
+    _fields_ = [("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("out_core", ctypes.c_void_p), ("tag", ctypes.c_int64)]
+
+
+class Completion(ctypes.Structure):
+    """C ``pico_completion``."""
+    _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_launch_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServerStatus(ctypes.Structure):
+    """C ``pico_server_status``."""
+    _fields_ = [(f, ctypes.c_int64) for f in ("waiting", "inflight", "ready", "busy_slots",
+                                               "launches", "completed", "arena_used",
+                                               "arena_bytes")]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class KernelStat(ctypes.Structure):
@@ -91,6 +161,29 @@ def load_library():
     lib.pico_last_error.restype = ctypes.c_char_p
     lib.pico_version.argtypes = []
     lib.pico_version.restype = ctypes.c_char_p
+    lib.pico_batched_workspace_bytes.argtypes = [i64, i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pico_batched_workspace_bytes.restype = i32
+    lib.pico_coreness_batched.argtypes = [vp, vp, vp, i64, i64, i64, i32, vp, vp,
+                                          ctypes.POINTER(BatchTune), vp, ctypes.c_size_t,
+                                          ctypes.POINTER(BatchStats), vp]
+    lib.pico_coreness_batched.restype = i32
+    lib.pico_task_scratch_bytes.argtypes = [i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pico_task_scratch_bytes.restype = i32
+    lib.pico_tasks_workspace_bytes.argtypes = [i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pico_tasks_workspace_bytes.restype = i32
+    lib.pico_coreness_tasks.argtypes = [ctypes.POINTER(Task), i64, i32, ctypes.POINTER(BatchTune), vp,
+                                        ctypes.c_size_t, ctypes.POINTER(BatchStats), vp]
+    lib.pico_coreness_tasks.restype = i32
+    lib.pico_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.pico_server_create.restype = i32
+    lib.pico_server_submit.argtypes = [vp, ctypes.POINTER(Request)]
+    lib.pico_server_submit.restype = i32
+    lib.pico_server_progress.argtypes = [vp, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32)]
+    lib.pico_server_progress.restype = i32
+    lib.pico_server_query.argtypes = [vp, ctypes.POINTER(ServerStatus)]
+    lib.pico_server_query.restype = i32
+    lib.pico_server_destroy.argtypes = [vp]
+    lib.pico_server_destroy.restype = i32
     lib.pico_profile_enable.argtypes = [i32]
     lib.pico_profile_enable.restype = i32
     lib.pico_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -172,6 +265,81 @@ def pico_profile_read() -> dict:
     return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(count.value)}
 
 
+def pico_batched_workspace_bytes(num_graphs: int, total_n: int, total_m: int, algo: int) -> int:
+    """C ``pico_batched_workspace_bytes``; raises PicoError on a bad status."""
+    out = ctypes.c_size_t(0)
+    _check(load_library().pico_batched_workspace_bytes(num_graphs, total_n, total_m, algo,
+                                                       ctypes.byref(out)))
+    return out.value
+
+
+def pico_task_scratch_bytes(n: int, m: int, algo: int) -> int:
+    """C ``pico_task_scratch_bytes``; raises PicoError on a bad status."""
+    out = ctypes.c_size_t(0)
+    _check(load_library().pico_task_scratch_bytes(n, m, algo, ctypes.byref(out)))
+    return out.value
+
+
+def pico_tasks_workspace_bytes(num_tasks: int) -> int:
+    """C ``pico_tasks_workspace_bytes``; raises PicoError on a bad status."""
+    out = ctypes.c_size_t(0)
+    _check(load_library().pico_tasks_workspace_bytes(num_tasks, ctypes.byref(out)))
+    return out.value
+
+
+def pico_coreness_tasks(tasks, algo: int, tune: BatchTune | None, workspace, ws_bytes: int,
+                        stats: BatchStats | None = None, stream=None) -> int:
+    """C ``pico_coreness_tasks`` over a sequence of Task; returns the status code."""
+    arr = (Task * max(len(tasks), 1))(*tasks)
+    return load_library().pico_coreness_tasks(arr, len(tasks), algo,
+                                              ctypes.byref(tune) if tune is not None else None,
+                                              _ptr(workspace), ws_bytes,
+                                              ctypes.byref(stats) if stats is not None else None,
+                                              _stream(stream))
+
+
+def pico_coreness_batched(graph_vptr, csr_offsets, csr_cols, num_graphs: int, total_n: int,
+                          total_m: int, algo: int, order, out_core, tune: BatchTune | None,
+                          workspace, ws_bytes: int, stats: BatchStats | None = None,
+                          stream=None) -> int:
+    """C ``pico_coreness_batched``; returns the status code (does not raise)."""
+    lib = load_library()
+    return lib.pico_coreness_batched(_ptr(graph_vptr), _ptr(csr_offsets), _ptr(csr_cols),
+                                     num_graphs, total_n, total_m, algo, _ptr(order),
+                                     _ptr(out_core), ctypes.byref(tune) if tune is not None else None,
+                                     _ptr(workspace), ws_bytes,
+                                     ctypes.byref(stats) if stats is not None else None,
+                                     _stream(stream))
+
+
+def largest_first(vptr: torch.Tensor) -> torch.Tensor:
+    """Processing order for a batch: graphs by decreasing vertex count."""
+    sizes = vptr[1:] - vptr[:-1]
+    return torch.argsort(sizes, descending=True, stable=True).to(torch.int32)
+
+
+def coreness_batched(batch, algo="peelone", *, order="largest_first", tune=None, out=None,
+                     workspace=None, with_stats: bool = False, stream=None):
+    """Coreness of every vertex of a device-resident packed batch (object with
+    vptr, offsets, cols tensors).  Raises PicoError on failure; waits for the
+    result when with_stats is set, otherwise returns once enqueued."""
+    a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    G = batch.vptr.numel() - 1
+    total_n = batch.offsets.numel() - 1
+    total_m = batch.cols.numel()
+    if isinstance(order, str):
+        order = largest_first(batch.vptr)
+    if out is None:
+        out = torch.empty(max(total_n, 0), dtype=torch.int32, device=batch.offsets.device)
+    if workspace is None:
+        nbytes = pico_batched_workspace_bytes(G, total_n, total_m, a)
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=batch.offsets.device)
+    st = BatchStats() if with_stats else None
+    _check(pico_coreness_batched(batch.vptr, batch.offsets, batch.cols, G, total_n, total_m, a, order,
+                                 out, tune, workspace, workspace.numel(), st, stream=stream))
+    return (out, st.as_dict()) if with_stats else out
+
+
 def pico_validate_csr(csr_offsets, csr_cols, n: int, m: int, algo: int, stream=None) -> int:
     """C ``pico_validate_csr``; returns the status code."""
     return load_library().pico_validate_csr(_ptr(csr_offsets), _ptr(csr_cols), n, m, algo,
@@ -213,3 +381,102 @@ def coreness(offsets: torch.Tensor, cols: torch.Tensor, algo="peelone", *, out=N
     _check(pico_coreness_ws(offsets, cols, n, m, a, out, workspace, workspace.numel(), st,
                             stream=stream))
     return (out, st.as_dict()) if with_stats else out
+
+
+def pico_server_create(cfg: ServerConfig):
+    """C ``pico_server_create``: returns (status, handle)."""
+    h = ctypes.c_void_p(0)
+    rc = load_library().pico_server_create(ctypes.byref(cfg), ctypes.byref(h))
+    return rc, h
+
+
+def pico_server_submit(handle, req: Request) -> int:
+    """C ``pico_server_submit``; returns the status code."""
+    return load_library().pico_server_submit(handle, ctypes.byref(req))
+
+
+def pico_server_progress(handle, done, max_done: int):
+    """C ``pico_server_progress`` into a ctypes array of Completion: returns
+    (status, number of completions written)."""
+    nd = ctypes.c_int(0)
+    rc = load_library().pico_server_progress(handle, done, max_done, ctypes.byref(nd))
+    return rc, nd.value
+
+
+def pico_server_query(handle):
+    """C ``pico_server_query``: returns (status, ServerStatus)."""
+    st = ServerStatus()
+    rc = load_library().pico_server_query(handle, ctypes.byref(st))
+    return rc, st
+
+
+def pico_server_destroy(handle) -> int:
+    """C ``pico_server_destroy``; returns the status code."""
+    return load_library().pico_server_destroy(handle)
+
+
+class Server:
+    """The C request server (``pico_server_*``) over a torch-allocated arena.
+
+    ``submit`` queues a request for a device-resident graph (int64 offsets)
+    and a device output; ``progress`` reaps, launches and returns completions
+    as a list of Completion.  ``close`` waits for launches in flight."""
+
+    def __init__(self, algo="peelone", *, arena_bytes: int, max_inflight: int = 4,
+                 max_tasks_per_launch: int = 4096, tune: BatchTune | None = None,
+                 device=None):
+        lib = load_library()
+        self._arena = torch.empty(max(arena_bytes, 256), dtype=torch.uint8, device=device or "cuda")
+        cfg = ServerConfig()
+        cfg.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        cfg.max_inflight = max_inflight
+        cfg.max_tasks_per_launch = max_tasks_per_launch
+        cfg.arena = self._arena.data_ptr()
+        cfg.arena_bytes = arena_bytes
+        cfg.tune = tune if tune is not None else BatchTune()
+        h = ctypes.c_void_p(0)
+        torch.cuda.synchronize()
+        _check(lib.pico_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self._buf = (Completion * 4096)()
+        self._nd = ctypes.c_int(0)
+        self._req = Request()
+
+    def submit(self, offsets, cols, n: int, m: int, out_core, tag: int) -> None:
+        r = self._req
+        r.offsets, r.cols, r.n, r.m = _ptr(offsets), _ptr(cols), n, m
+        r.out_core, r.tag = _ptr(out_core), tag
+        _check(self._lib.pico_server_submit(self._h, ctypes.byref(r)))
+
+    def submit_ptrs(self, offsets: int, cols: int, n: int, m: int, out_core: int, tag: int) -> None:
+        r = self._req
+        r.offsets, r.cols, r.n, r.m, r.out_core, r.tag = offsets, cols, n, m, out_core, tag
+        _check(self._lib.pico_server_submit(self._h, ctypes.byref(r)))
+
+    def progress(self) -> list:
+        _check(self._lib.pico_server_progress(self._h, self._buf, len(self._buf),
+                                              ctypes.byref(self._nd)))
+        return [self._buf[i] for i in range(self._nd.value)]
+
+    def progress_raw(self):
+        """(count, buffer): completions stay in the shared buffer until the next call."""
+        _check(self._lib.pico_server_progress(self._h, self._buf, len(self._buf),
+                                              ctypes.byref(self._nd)))
+        return self._nd.value, self._buf
+
+    def status(self) -> dict:
+        st = ServerStatus()
+        _check(self._lib.pico_server_query(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(self._lib.pico_server_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -132,21 +132,6 @@ int prof_resolve() {
     return rc;
 }
 
-int check_device() {
-    int dev = -1;
-    PICO_HIP_TRY(hipGetDevice(&dev));
-    static int checked[64] = {0};  // 0 unknown, 1 ok, -1 unsupported
-    if (dev >= 0 && dev < 64 && checked[dev] != 0) return checked[dev] > 0 ? PICO_OK : PICO_ENOTSUP;
-    hipDeviceProp_t prop;
-    PICO_HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    if (dev >= 0 && dev < 64) checked[dev] = ok ? 1 : -1;
-    if (!ok) {
-        set_error("device %d is %s; this library is built for gfx950 only", dev, prop.gcnArchName);
-        return PICO_ENOTSUP;
-    }
-    return PICO_OK;
-}
 
 int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo,
                const int32_t *out) {
@@ -224,6 +209,22 @@ __global__ void validate_kernel(const Off *__restrict__ off, const int32_t *__re
 
 }  // namespace
 
+int check_device() {
+    int dev = -1;
+    PICO_HIP_TRY(hipGetDevice(&dev));
+    static int checked[64] = {0};  // 0 unknown, 1 ok, -1 unsupported
+    if (dev >= 0 && dev < 64 && checked[dev] != 0) return checked[dev] > 0 ? PICO_OK : PICO_ENOTSUP;
+    hipDeviceProp_t prop;
+    PICO_HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev >= 0 && dev < 64) checked[dev] = ok ? 1 : -1;
+    if (!ok) {
+        set_error("device %d is %s; this library is built for gfx950 only", dev, prop.gcnArchName);
+        return PICO_ENOTSUP;
+    }
+    return PICO_OK;
+}
+
 int prof_begin(const char *name, hipStream_t s) {
     if (!g_prof.on) return -1;
     ProfRec r{name, prof_event(), prof_event()};
@@ -240,6 +241,14 @@ void prof_end(int rec, hipStream_t s) {
 }  // namespace pico
 
 using namespace pico;
+
+static bool tune_ok(const pico_batch_tune *tune) {
+    if (tune && tune->reserved != 0) {
+        set_error("pico_batch_tune.reserved must be 0");
+        return false;
+    }
+    return true;
+}
 
 extern "C" {
 
@@ -355,6 +364,155 @@ int pico_coreness(const void *csr_offsets, const int32_t *csr_cols, int64_t n, i
     }
     PICO_HIP_TRY(hipStreamSynchronize(s));
     return prof_resolve();
+}
+
+int pico_batched_workspace_bytes(int64_t num_graphs, int64_t total_n, int64_t total_m, int algo,
+                                 size_t *bytes) {
+    clear_error();
+    int a = algo & PICO_ALGO_MASK;
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) || num_graphs < 0 || total_n < 0 ||
+        total_m < 0 || !bytes) {
+        set_error("bad arguments to pico_batched_workspace_bytes");
+        return PICO_EINVAL;
+    }
+    *bytes = batched_ws_bytes(num_graphs, total_n, total_m, algo);
+    return PICO_OK;
+}
+
+int pico_coreness_batched(const int64_t *graph_vptr, const int64_t *csr_offsets,
+                          const int32_t *csr_cols, int64_t num_graphs, int64_t total_n,
+                          int64_t total_m, int algo, const int32_t *order, int32_t *out_core,
+                          const pico_batch_tune *tune, void *workspace, size_t ws_bytes,
+                          pico_batch_stats *stats, void *stream) {
+    clear_error();
+    if (stats) memset(stats, 0, sizeof(*stats));
+    int a = algo & PICO_ALGO_MASK;
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) ||
+        (algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64)) != 0) {
+        set_error("unknown algo %d", algo);
+        return PICO_EINVAL;
+    }
+    if (num_graphs < 0 || total_n < 0 || total_m < 0) {
+        set_error("negative size");
+        return PICO_EINVAL;
+    }
+    if (!tune_ok(tune)) return PICO_EINVAL;
+    if (num_graphs == 0) return PICO_OK;
+    if (!graph_vptr || (total_n > 0 && (!csr_offsets || !out_core)) || (total_m > 0 && !csr_cols)) {
+        set_error("NULL pointer with a non-empty batch");
+        return PICO_EINVAL;
+    }
+    int rc = check_device();
+    if (rc) return rc;
+    size_t need = batched_ws_bytes(num_graphs, total_n, total_m, algo);
+    if (!workspace || ws_bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws_bytes, need);
+        return PICO_ENOMEM;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return PICO_EINVAL;
+    }
+    rc = run_batched(reinterpret_cast<const long long *>(graph_vptr),
+                     reinterpret_cast<const long long *>(csr_offsets), csr_cols, num_graphs, total_n,
+                     total_m, a, order, out_core, workspace, ws_bytes, tune, stats,
+                     static_cast<hipStream_t>(stream));
+    if (rc) {
+        g_prof.pending.clear();
+        g_prof.used = 0;
+        return rc;
+    }
+    if (g_prof.on) {
+        PICO_HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+        return prof_resolve();
+    }
+    return PICO_OK;
+}
+
+
+int pico_task_scratch_bytes(int64_t n, int64_t m, int algo, size_t *bytes) {
+    clear_error();
+    int a = algo & PICO_ALGO_MASK;
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) || n < 0 || n > INT32_MAX || m < 0 ||
+        !bytes) {
+        set_error("bad arguments to pico_task_scratch_bytes");
+        return PICO_EINVAL;
+    }
+    *bytes = task_scratch_bytes(n, m, a);
+    return PICO_OK;
+}
+
+int pico_tasks_workspace_bytes(int64_t num_tasks, size_t *bytes) {
+    clear_error();
+    if (num_tasks < 0 || !bytes) {
+        set_error("bad arguments to pico_tasks_workspace_bytes");
+        return PICO_EINVAL;
+    }
+    *bytes = tasks_ws_bytes(num_tasks);
+    return PICO_OK;
+}
+
+int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int algo,
+                        const pico_batch_tune *tune, void *workspace, size_t ws_bytes,
+                        pico_batch_stats *stats, void *stream) {
+    clear_error();
+    if (stats) memset(stats, 0, sizeof(*stats));
+    int a = algo & PICO_ALGO_MASK;
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) ||
+        (algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64)) != 0) {
+        set_error("unknown algo %d", algo);
+        return PICO_EINVAL;
+    }
+    if (num_tasks < 0 || (num_tasks > 0 && !tasks) || !tune_ok(tune)) {
+        if (num_tasks < 0 || (num_tasks > 0 && !tasks)) set_error("bad task list");
+        return PICO_EINVAL;
+    }
+    if (num_tasks == 0) return PICO_OK;
+    for (int64_t i = 0; i < num_tasks; ++i) {
+        const pico_task &t = tasks[i];
+        if (t.n < 0 || t.n > INT32_MAX || t.m < 0 || (t.n > 0 && (!t.offsets || !t.out_core)) ||
+            (t.m > 0 && !t.cols)) {
+            set_error("task %lld: bad sizes or NULL pointer (n %lld, m %lld)", (long long)i,
+                      (long long)t.n, (long long)t.m);
+            return PICO_EINVAL;
+        }
+        if (t.n == 0) continue;
+        const size_t need = task_scratch_bytes(t.n, t.m, a);
+        if (!t.scratch || t.scratch_bytes < need) {
+            set_error("task %lld: scratch of %zu bytes given, %zu needed", (long long)i,
+                      t.scratch_bytes, need);
+            return PICO_ENOMEM;
+        }
+        if (((uintptr_t)t.scratch & 255) != 0) {
+            set_error("task %lld: scratch must be 256-byte aligned", (long long)i);
+            return PICO_EINVAL;
+        }
+    }
+    int rc = check_device();
+    if (rc) return rc;
+    const size_t need = tasks_ws_bytes(num_tasks);
+    if (!workspace || ws_bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws_bytes, need);
+        return PICO_ENOMEM;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return PICO_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pico_task *dev = tasks_table(workspace, ws_bytes, num_tasks);
+    PICO_HIP_TRY(hipMemcpyAsync(dev, tasks, sizeof(pico_task) * num_tasks, hipMemcpyHostToDevice, s));
+    rc = run_tasks_device(dev, num_tasks, a, workspace, ws_bytes, tune, stats, s);
+    if (rc) {
+        g_prof.pending.clear();
+        g_prof.used = 0;
+        return rc;
+    }
+    if (g_prof.on) {
+        PICO_HIP_TRY(hipStreamSynchronize(s));
+        return prof_resolve();
+    }
+    return PICO_OK;
 }
 
 int pico_validate_csr(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,

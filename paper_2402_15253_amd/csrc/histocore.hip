@@ -449,8 +449,11 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
     if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[1].v);
 
-    // Round r's frontier: entries [0, nf) of buffer r & 1, edge space [e0, e1).
-    unsigned long long fbase = 0, e0 = 0;
+    // Round r's frontier: entries [0, nf) of buffer r & 1, edge space [0, e1).
+    // The packed counter restarts from zero every round (block 0 clears it
+    // before SumHisto; the next pushes come after two more barriers), so its
+    // fields hold one round's slots (<= n) and edges (<= m), not running sums
+    // over all rounds, which would outgrow the edge field on large graphs.
     long long nf = (long long)(snap[FET] & kSlotMask);
     unsigned long long e1 = snap[FET] >> kSlotBits;
     const long long first = nf;
@@ -459,6 +462,7 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
         const int cur = r & 1, nxt = cur ^ 1;
         ++rounds;
         ftotal += nf;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(&gs->ctr[FET].v, 0ull);
         const unsigned long long hs0 = snap[HS_TAIL];
         sum_histo<Off>(a, a.F[cur], a.FR[cur], nf, nbuck);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
@@ -466,9 +470,9 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
         sum_heavy<Off>(a, a.F[cur], a.FR[cur], hs0, snap[HS_TAIL], part, &first_ok);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[3].v);
-        const unsigned long long fnext = snap[FET] & kSlotMask;
-        nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? (long long)(e1 - e0) : 0;
-        edge_balanced(a.F[cur], a.FE[cur], a.FR[cur], a.P0, a.P1, 0, nf, (long long)e0, (long long)e1,
+        const unsigned long long fnext = snap[FET] & kSlotMask;  // 0: cleared this round
+        nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? (long long)e1 : 0;
+        edge_balanced(a.F[cur], a.FE[cur], a.FR[cur], a.P0, a.P1, 0, nf, 0ll, (long long)e1,
                       a.cols, a.ndeg, eb,
                       [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR],
                           EbLds &L, const int (&du)[kEbR]) {
@@ -483,11 +487,8 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[4].v);
         nf = (long long)((snap[FET] & kSlotMask) - fnext);
-        fbase = fnext;
-        e0 = e1;
         e1 = snap[FET] >> kSlotBits;
     }
-    (void)fbase;
     flush_count(nmove, &gs->ctr[N_MOVES].v);
     flush_count(nedge, &gs->ctr[N_EDGES].v);
     flush_count(nbuck, &gs->ctr[N_BUCKETS].v);

@@ -52,3 +52,36 @@ def test_argument_errors_need_no_device():
     assert pico.pico_coreness(None, None, 0, 0, 7, None) == pico.PICO_EINVAL
     assert pico.pico_coreness(None, None, 0, 0, 0, None) == pico.PICO_OK  # n == 0: no-op
     assert pico.pico_coreness_ws(None, None, 0, 0, 1, None, None, 0) == pico.PICO_OK
+
+
+def test_task_and_server_argument_checks_need_no_device():
+    pe, hc = pico.PICO_ALGO_PEELONE, pico.PICO_ALGO_HISTOCORE
+    # per-task scratch: four int32 arrays of n (PeelOne), plus oldcore n and histogram m
+    assert pico.pico_task_scratch_bytes(1000, 8000, pe) == 4 * 1024 * 4
+    assert pico.pico_task_scratch_bytes(1000, 8000, hc) == (5 * 1024 + 8000) * 4
+    assert pico.pico_task_scratch_bytes(0, 0, pe) == 0
+    with pytest.raises(pico.PicoError):
+        pico.pico_task_scratch_bytes(2**31, 0, pe)
+    assert pico.pico_tasks_workspace_bytes(100) > 100 * ctypes.sizeof(pico.Task)
+    assert ctypes.sizeof(pico.Task) == 56 and ctypes.sizeof(pico.BatchTune) == 16
+    assert ctypes.sizeof(pico.BatchStats) == 9 * 8 + 8
+    assert ctypes.sizeof(pico.Completion) == 40
+    # bad task lists are rejected on the host, before any device work
+    bad = pico.Task(None, None, -1, 0, None, None, 0)
+    assert pico.pico_coreness_tasks([bad], pe, None, None, 0) == pico.PICO_EINVAL
+    assert "task 0" in pico.pico_last_error()
+    short = pico.Task(1, 1, 10, 40, 1, 256, 100)  # scratch too small: never dereferenced
+    assert pico.pico_coreness_tasks([short], pe, None, None, 0) == pico.PICO_ENOMEM
+    assert pico.pico_coreness_tasks([], pe, None, None, 0) == pico.PICO_OK
+    tune = pico.BatchTune()
+    tune.reserved = 1
+    assert pico.pico_coreness_tasks([], pe, tune, None, 0) == pico.PICO_EINVAL
+    # server configuration errors come before the device check
+    cfg = pico.ServerConfig()
+    cfg.algo, cfg.max_inflight, cfg.max_tasks_per_launch = 7, 2, 16
+    assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
+    cfg.algo, cfg.max_inflight = pe, 0
+    assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
+    cfg.max_inflight, cfg.arena, cfg.arena_bytes = 2, 4096 + 8, 1 << 20  # misaligned arena
+    assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
+    assert pico.pico_server_destroy(None) == pico.PICO_OK

@@ -1,0 +1,126 @@
+"""GPU parity of the task-list entry point and the request server: every
+request's coreness is the oracle's, and the same whether the graph is
+decomposed alone or in a mix of requests that are admitted, batched and run
+concurrently by the server."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2402_15253_amd as pico
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pool():
+    """A device-resident pool of graphs of mixed size (some above the LDS
+    tier, some empty or edgeless) with their oracle coreness."""
+    b = gg.mixed_batch(40, 2, 40_000, seed=77, device="cuda")
+    graphs = []
+    for g in range(b.num_graphs):
+        x0, x1 = int(b.vptr[g]), int(b.vptr[g + 1])
+        off = b.offsets[x0:x1 + 1]  # positions into b.cols, not starting at 0
+        m = int(off[-1] - off[0]) if x1 > x0 else 0
+        cpu = b.graph(g)
+        want = oracle.bz_coreness(cpu.offsets.cpu(), cpu.cols.cpu())
+        graphs.append({"off": off, "n": x1 - x0, "m": m, "want": want})
+    return b, graphs
+
+
+def _scratch(n, m, algo):
+    nbytes = pico.pico_task_scratch_bytes(n, m, algo)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("algo", ["peelone", "histocore"])
+def test_tasks_match_oracle(pool, algo):
+    b, graphs = pool
+    code = pico.ALGOS[algo]
+    keep, tasks = [], []
+    order = sorted(range(len(graphs)), key=lambda i: -graphs[i]["n"])
+    for i in order:
+        g = graphs[i]
+        out = torch.full((max(g["n"], 1),), -1, dtype=torch.int32, device="cuda")
+        s = _scratch(g["n"], g["m"], code)
+        keep.append((i, out, s))
+        tasks.append(pico.Task(g["off"].data_ptr(), b.cols.data_ptr(), g["n"], g["m"], out.data_ptr(),
+                               s.data_ptr(), s.numel()))
+    wsb = pico.pico_tasks_workspace_bytes(len(tasks))
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    st = pico.BatchStats()
+    rc = pico.pico_coreness_tasks(tasks, code, pico.BatchTune(), ws, wsb, st)
+    assert rc == pico.PICO_OK, pico.pico_last_error()
+    print(f"{algo} stats={st.as_dict()}", flush=True)
+    for i, out, _ in keep:
+        g = graphs[i]
+        assert np.array_equal(out[:g["n"]].cpu().numpy(), g["want"]), f"graph {i} n={g['n']}"
+    assert st.graphs == len(tasks) and st.lds_graphs > 0 and st.lds_graphs < len(tasks)
+
+
+@pytest.mark.parametrize("algo", ["peelone", "histocore"])
+def test_server_alone_vs_mix(pool, algo):
+    """Requests arrive in bursts while earlier ones run; the arena admits only
+    part of them at a time, and up to three launches are in flight.  Each
+    result equals the graph's result alone (the plain single-graph call) and
+    the oracle's."""
+    b, graphs = pool
+    code = pico.ALGOS[algo]
+    alone = []
+    for g in graphs:
+        if g["n"] == 0:
+            alone.append(np.zeros(0, dtype=np.int32))
+            continue
+        off = (g["off"] - g["off"][0]).contiguous()
+        e0 = int(g["off"][0])
+        core = pico.coreness(off, b.cols[e0:e0 + g["m"]], algo)
+        alone.append(core.cpu().numpy())
+    for g, a in zip(graphs, alone):
+        assert np.array_equal(a, g["want"])
+    need = [pico.pico_task_scratch_bytes(g["n"], g["m"], code) for g in graphs]
+    arena = max(3 * max(need), 1 << 20)  # well below the sum over all requests
+    srv = pico.Server(algo, arena_bytes=arena, max_inflight=3, max_tasks_per_launch=16)
+    rng = np.random.default_rng(5)
+    R = 300
+    pick = rng.integers(0, len(graphs), R)
+    sizes = [graphs[p]["n"] for p in pick]
+    base = np.concatenate([[0], np.cumsum(sizes)])
+    out = torch.full((int(base[-1]) + 1,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # the server runs on its own streams
+    done, r, peak_wait = {}, 0, 0
+    while len(done) < R:
+        burst = int(rng.integers(1, 12))
+        for _ in range(burst):
+            if r == R:
+                break
+            g = graphs[pick[r]]
+            srv.submit_ptrs(g["off"].data_ptr(), b.cols.data_ptr(), g["n"], g["m"],
+                            out.data_ptr() + 4 * int(base[r]), r)
+            r += 1
+        for c in srv.progress():
+            assert c.status == pico.PICO_OK
+            assert c.tag not in done
+            assert c.t_submit_ns <= c.t_launch_ns <= c.t_done_ns
+            done[c.tag] = c
+        peak_wait = max(peak_wait, srv.status()["waiting"])
+    st = srv.status()
+    srv.close()
+    assert st["completed"] == R and st["arena_used"] == 0 and st["waiting"] == 0
+    assert st["launches"] > 1
+    print(f"{algo}: {st} peak waiting {peak_wait}", flush=True)
+    got = out.cpu().numpy()
+    for i in range(R):
+        p = pick[i]
+        assert np.array_equal(got[base[i]:base[i + 1]], alone[p]), f"request {i} graph {p}"
+
+
+def test_server_rejects_what_never_fits(pool):
+    b, graphs = pool
+    g = max(graphs, key=lambda g: g["n"])
+    srv = pico.Server("peelone", arena_bytes=1 << 16, max_inflight=1, max_tasks_per_launch=4)
+    out = torch.empty(g["n"], dtype=torch.int32, device="cuda")
+    with pytest.raises(pico.PicoError) as e:
+        srv.submit(g["off"], b.cols, g["n"], g["m"], out, 0)
+    assert e.value.status == pico.PICO_ENOMEM
+    srv.close()
