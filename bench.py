@@ -115,10 +115,19 @@ def cpu_baseline(g, budget_s: float):
     return core, runs, t_total
 
 
-def _roofline(kname: str, alg_bytes: float, avg_ms: float) -> dict:
+def recorded_traffic(kernel: str, config: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summaries
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if there is none for
+    this kernel and workload or the kernel's sources changed since."""
+    from paper_2402_15253_amd.profiling import recorded_traffic as rt
+    return rt(kernel, config)
+
+
+def _roofline(kname: str, alg_bytes: float, avg_ms: float, config: str = "") -> dict:
     gbps = alg_bytes / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(kname, config),
+            "kernel": kname,
             "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(alg_bytes)}
 
 
@@ -228,13 +237,16 @@ def bench_batched(args, pico, torch, np):
                 if rc != pico.PICO_OK:
                     raise pico.PicoError(rc, pico.pico_last_error())
 
-        plain_pass()  # warm-up
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        plain_pass()
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - tp0
-        same = bool(torch.equal(out_b, out_p))
+        if args.no_plain:
+            t_plain, same = float("nan"), True
+        else:
+            plain_pass()  # warm-up
+            torch.cuda.synchronize()
+            tp0 = time.perf_counter()
+            plain_pass()
+            torch.cuda.synchronize()
+            t_plain = time.perf_counter() - tp0
+            same = bool(torch.equal(out_b, out_p))
         sd = st.as_dict()
         per[a] = {"batched_ms": round(t_batched * 1e3, 3), "plain_ms": round(t_plain * 1e3, 1),
                   "batched_graphs_per_s": round(G / t_batched, 1),
@@ -246,10 +258,17 @@ def bench_batched(args, pico, torch, np):
             launches, t_ms = prof["batched_kernel"]
             avg = t_ms / max(launches, 1)
             kern[a] = _roofline("batched_kernel", algorithmic_bytes(a, _batch_stats_as_plain(sd),
-                                                                    total_n, total_m, 8), avg)
+                                                                    total_n, total_m, 8), avg,
+                                f"batched_{a}")
         outs[a] = out_b
         log(f"{a}: {per[a]}")
         del ws
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     value = len(algos) * G / sum(per[a]["batched_ms"] / 1e3 for a in algos)
     plain = len(algos) * G / sum(per[a]["plain_ms"] / 1e3 for a in algos)
     roof = max(kern.values(), key=lambda r: r["avg_launch_ms"]) if kern else None
@@ -449,6 +468,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="batched: skip the autotuner and use the default launch parameters")
     ap.add_argument("--graphs", type=int, default=4096, help="batched: number of graphs")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched: skip the per-graph plain-call comparison (profiling runs)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serving: trace length (s)")
     ap.add_argument("--pool", type=int, default=2048, help="serving: graphs in the request pool")
@@ -535,7 +556,8 @@ def main():
         kname = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"] * per_kernel[k]["launches"])
         pk = per_kernel[kname]
         roofline = {"bound": "hbm", "achieved": pk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(pk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(pk["alg_GBps"] / HBM_PEAK_GBS, 4),
+                    "traffic": recorded_traffic(kname, args.config),
                     "kernel": kname, "avg_launch_ms": pk["avg_ms"],
                     "algorithmic_bytes_per_launch": pk["alg_bytes"]}
 

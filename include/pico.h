@@ -249,13 +249,17 @@ PICO_API int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int 
  * Request server: continuous batching of decomposition requests on one GPU.
  * Requests name a device-resident graph (int64 offsets, as in pico_task) and
  * a device output.  A request is admitted once its scratch
- * (pico_task_scratch_bytes) fits in the caller's HBM arena; admitted requests
- * are launched together, largest first, as one batched-kernel call on a free
- * launch slot (one HIP stream each, up to max_inflight in flight), so
- * requests that arrive while others run start on a free slot at once and
- * overlap with them on the device.  Admission is first come, first served.
- * The caller drives it: submit queues, progress reaps finished launches,
- * launches what fits and returns completions.  Single host thread per server.
+ * (pico_task_scratch_bytes) fits in the caller's HBM arena (first come,
+ * first served within its size class); admitted requests are launched
+ * together, largest first, as one batched-kernel call on a free launch slot
+ * (one HIP stream each, up to max_inflight launches in flight), so requests
+ * that arrive while others run start on a free slot at once and overlap with
+ * them on the device.  A launch holds requests of one size class only
+ * (vertex counts below class_bounds[0], below class_bounds[1], the rest), so
+ * small requests never wait for a large graph in their launch; large requests
+ * hold at most max_large_slots slots.  The caller drives it: submit queues,
+ * progress reaps finished launches, launches what fits and returns
+ * completions.  Single host thread per server.
  */
 typedef struct pico_server pico_server;
 
@@ -267,6 +271,10 @@ typedef struct pico_server_config {
                                       admission budget for request scratch */
     size_t arena_bytes;
     pico_batch_tune tune;          /* batched-kernel tuning (zeros / -1 = defaults) */
+    int64_t class_bounds[2];       /* vertex-count bounds of the small and medium
+                                      classes; 0 = 16384 and 131072 */
+    int32_t max_large_slots;       /* slots the large class may hold; 0 = half */
+    int32_t reserved;              /* must be 0 */
 } pico_server_config;
 
 typedef struct pico_request {
@@ -296,11 +304,12 @@ PICO_API int pico_server_create(const pico_server_config *cfg, pico_server **ser
 /* pico_server_submit -- queue one request (host-checked; PICO_ENOMEM if its
    scratch can never fit the arena).  Does not touch the device. */
 PICO_API int pico_server_submit(pico_server *server, const pico_request *req);
-/* pico_server_progress -- reap, launch, and copy up to max_done completions
-   into done (host array); *num_done gets the count.  Never blocks. */
+/* pico_server_progress -- reap finished launches, launch what fits on free
+   slots, and copy up to max_done completions into done (host array);
+   *num_done gets the count.  Never blocks. */
 PICO_API int pico_server_progress(pico_server *server, pico_completion *done, int max_done,
                                   int *num_done);
-/* pico_server_query -- queue lengths, launches so far and arena use. */
+/* pico_server_query -- queue lengths, busy slots, launches so far and arena use. */
 PICO_API int pico_server_query(const pico_server *server, pico_server_status *status);
 /* pico_server_destroy -- wait for launches in flight, release everything the
    server allocated; requests still waiting are dropped. */

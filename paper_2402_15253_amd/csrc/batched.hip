@@ -57,6 +57,10 @@ struct BatchArgs {
     BatchState *st;
 };
 
+// Scratch layout of one public task: core, L0, L1, L2 (n each), then for
+// HistoCore oldcore (n) and the histogram (m), each 256-byte aligned.
+__host__ __device__ inline long long task_al(long long count) { return (count + 63) & ~63ll; }
+
 // Per-thread event counts, summed once per workgroup at exit.
 struct Counts {
     long long levels = 0, atomics = 0, lds = 0, frontier = 0, edges = 0, buckets = 0, pushes = 0;
@@ -391,6 +395,21 @@ __device__ void histo_graph(const Task &t, int sum_wave_min, WgCounters &w, Expa
     __syncthreads();
 }
 
+// One graph, by the workgroup: LDS tier if its values fit.
+__device__ __forceinline__ void decompose(const Task &t, int algo, int lds_cap, int sum_wave_min,
+                                          WgCounters &w, ExpandLds &X, Counts &c) {
+    if (t.n <= 0) return;
+    const bool lds = t.n <= lds_cap;
+    c.lds += lds ? 1 : 0;
+    if (algo == PICO_ALGO_PEELONE) {
+        if (lds) peel_graph<true>(t, w, X, c);
+        else peel_graph<false>(t, w, X, c);
+    } else {
+        if (lds) histo_graph<true>(t, sum_wave_min, w, X, c);
+        else histo_graph<false>(t, sum_wave_min, w, X, c);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
     __shared__ WgCounters w;
     __shared__ ExpandLds X;
@@ -403,16 +422,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
         __syncthreads();
         if (j >= a.T) break;
         const Task t = a.tasks[j];
-        if (t.n <= 0) continue;
-        const bool lds = t.n <= a.lds_cap;
-        c.lds += lds ? 1 : 0;
-        if (a.algo == PICO_ALGO_PEELONE) {
-            if (lds) peel_graph<true>(t, w, X, c);
-            else peel_graph<false>(t, w, X, c);
-        } else {
-            if (lds) histo_graph<true>(t, a.sum_wave_min, w, X, c);
-            else histo_graph<false>(t, a.sum_wave_min, w, X, c);
-        }
+        decompose(t, a.algo, a.lds_cap, a.sum_wave_min, w, X, c);
     }
     // per-thread counts: atomics, edges, buckets, pushes; per-workgroup
     // (uniform, thread 0's): levels, frontier, lds graphs
@@ -472,9 +482,6 @@ __global__ void packed_tasks(PackedArrays p, Task *tasks, BatchState *st) {
     tasks[j] = t;
 }
 
-// Scratch layout of one public task: core, L0, L1, L2 (n each), then for
-// HistoCore oldcore (n) and the histogram (m), each 256-byte aligned.
-__host__ __device__ inline long long task_al(long long count) { return (count + 63) & ~63ll; }
 
 __global__ void public_tasks(const pico_task *pt, long long T, int histocore, Task *tasks) {
     const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -504,7 +511,7 @@ struct Launch {
     long long blocks;
 };
 
-int launch_config(const pico_batch_tune *tune, long long T, Launch *L) {
+int launch_config(const void *kernel, const pico_batch_tune *tune, long long T, Launch *L) {
     int lds_bytes = tune && tune->lds_bytes >= 0 ? tune->lds_bytes : 64 * 1024;
     int dev = 0, cus = 0, max_dyn = 0;
     PICO_HIP_TRY(hipGetDevice(&dev));
@@ -515,12 +522,10 @@ int launch_config(const pico_batch_tune *tune, long long T, Launch *L) {
     if (lds_bytes < 0) lds_bytes = 0;
     lds_bytes &= ~3;
     if (lds_bytes > 48 * 1024)
-        PICO_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(batched_kernel),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes));
+        PICO_HIP_TRY(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes));
     int per_cu = tune && tune->blocks_per_cu > 0 ? tune->blocks_per_cu : 0;
     int occ = 0;
-    PICO_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void *>(batched_kernel), kBlock, lds_bytes));
+    PICO_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kBlock, lds_bytes));
     if (occ < 1) occ = 1;
     if (per_cu == 0 || per_cu > occ) per_cu = occ;
     long long blocks = (long long)per_cu * cus;
@@ -534,7 +539,7 @@ int launch_config(const pico_batch_tune *tune, long long T, Launch *L) {
 int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune *tune,
                  BatchState *st, pico_batch_stats *stats, hipStream_t stream) {
     Launch L;
-    int rc = launch_config(tune, T, &L);
+    int rc = launch_config(reinterpret_cast<const void *>(batched_kernel), tune, T, &L);
     if (rc) return rc;
     BatchArgs a;
     a.tasks = tasks;

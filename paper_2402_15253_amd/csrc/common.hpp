@@ -559,6 +559,8 @@ pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T);
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
                      const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream);
 int check_device();
+
+
 int run_batched(const long long *vptr, const long long *off, const int32_t *cols, int64_t G,
                 int64_t total_n, int64_t total_m, int algo, const int32_t *order, int32_t *out,
                 void *ws, size_t ws_bytes, const pico_batch_tune *tune, pico_batch_stats *stats,

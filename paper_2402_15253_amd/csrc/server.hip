@@ -1,20 +1,30 @@
 // Request server: continuous batching of decomposition requests.
 //
 // Requests name a device-resident CSR graph and a device output.  A request
-// is admitted when its per-request scratch (the working arrays of the
-// decomposition) fits in the HBM arena the caller hands over; admitted
-// requests are launched together as one batched-kernel call on one of a few
-// launch slots (each its own stream), largest graph first.  A slot is reused
-// once its launch has completed, so requests that arrive while others run are
-// launched on a free slot right away and their work overlaps on the device
-// with the launches already in flight.  Completion is detected by polling an
-// event per slot; arena blocks are returned to the free list then.
+// is admitted when its per-request scratch (the decomposition's working
+// arrays) fits in the HBM arena the caller hands over.  Admitted requests are
+// launched together, largest first, as one batched-kernel call on a free
+// launch slot (each slot its own stream), and a slot is reused as soon as its
+// launch has completed, so requests that arrive while others run are launched
+// on a free slot right away and their work overlaps on the device with the
+// launches already in flight.
+//
+// A launch completes only with its slowest graph, so requests are kept in
+// three size classes (by vertex count) and a launch takes requests of one
+// class only: a small request never waits for a large graph of the same
+// launch.  Large requests may hold at most max_large_slots slots at a time,
+// so the small and medium classes always find a slot.  Among the classes
+// allowed on a free slot, the one whose oldest request has waited longest
+// goes first.
 //
 // The server is driven by the caller: pico_server_submit queues a request,
-// pico_server_progress reaps finished launches, launches what fits, and hands
-// back completions.  Nothing here blocks except pico_server_destroy.
+// pico_server_progress reaps finished launches (completion is an event per
+// slot), launches what fits, and hands back completions.  Nothing here blocks
+// except pico_server_destroy.
 #include <algorithm>
 #include <chrono>
+#include <climits>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <new>
@@ -23,13 +33,6 @@
 #include "common.hpp"
 
 namespace pico {
-
-size_t task_scratch_bytes(int64_t n, int64_t m, int algo);
-size_t tasks_ws_bytes(int64_t T);
-pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T);
-int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
-                     const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream);
-
 namespace {
 
 uint64_t now_ns() {
@@ -48,9 +51,9 @@ class Arena {
         if (cap_) free_[0] = cap_;
         used_ = 0;
     }
+    static size_t granule(size_t bytes) { return bytes ? (bytes + 255) & ~(size_t)255 : 256; }
     bool alloc(size_t bytes, size_t *off) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        if (bytes == 0) bytes = 256;
+        bytes = granule(bytes);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= bytes) {
                 *off = it->first;
@@ -64,8 +67,7 @@ class Arena {
         return false;
     }
     void release(size_t off, size_t bytes) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        if (bytes == 0) bytes = 256;
+        bytes = granule(bytes);
         used_ -= bytes;
         auto next = free_.lower_bound(off);
         if (next != free_.end() && off + bytes == next->first) {
@@ -89,6 +91,8 @@ class Arena {
     size_t cap_ = 0, used_ = 0;
 };
 
+constexpr int kClasses = 3;  // small, medium, large
+
 struct Req {
     pico_request r;
     size_t bytes = 0, arena_off = 0;
@@ -102,6 +106,7 @@ struct Slot {
     void *ws = nullptr;            // device tasks workspace
     size_t ws_bytes = 0;
     std::vector<Req> reqs;
+    int cls = 0;
     bool busy = false;
 };
 
@@ -111,15 +116,19 @@ struct Slot {
 struct pico_server {
     pico_server_config cfg;
     int device = 0;
+    int64_t bound[2] = {0, 0};  // vertex-count bounds of the small and medium classes
+    int max_large = 1;
     pico::Arena arena;
-    std::deque<pico::Req> waiting;
+    std::deque<pico::Req> waiting[pico::kClasses];
     std::deque<pico_completion> ready;
     std::vector<pico::Slot> slots;
-    int64_t launches = 0, launched_requests = 0, completed = 0;
+    int64_t launches = 0, completed = 0;
 };
 
 namespace pico {
 namespace {
+
+int class_of(const pico_server *s, int64_t n) { return n < s->bound[0] ? 0 : n < s->bound[1] ? 1 : 2; }
 
 void destroy_slots(pico_server *s) {
     for (Slot &sl : s->slots) {
@@ -160,16 +169,36 @@ int reap(pico_server *s) {
     return PICO_OK;
 }
 
-int launch(pico_server *s, Slot &sl) {
+// The class a free slot serves next: the allowed class whose oldest waiting
+// request was submitted first, or -1.
+int pick_class(const pico_server *s) {
+    int large_busy = 0;
+    for (const Slot &sl : s->slots) large_busy += (sl.busy && sl.cls == 2) ? 1 : 0;
+    int best = -1;
+    uint64_t t_best = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        if (s->waiting[c].empty()) continue;
+        if (c == 2 && large_busy >= s->max_large) continue;
+        const uint64_t t = s->waiting[c].front().t_submit;
+        if (best < 0 || t < t_best) {
+            best = c;
+            t_best = t;
+        }
+    }
+    return best;
+}
+
+int launch(pico_server *s, Slot &sl, int cls) {
     const int64_t cap = s->cfg.max_tasks_per_launch;
     char *base = static_cast<char *>(s->cfg.arena);
-    while (!s->waiting.empty() && (int64_t)sl.reqs.size() < cap) {
-        Req &r = s->waiting.front();
+    std::deque<Req> &q = s->waiting[cls];
+    while (!q.empty() && (int64_t)sl.reqs.size() < cap) {
+        Req &r = q.front();
         size_t off = 0;
         if (!s->arena.alloc(r.bytes, &off)) break;  // first come, first served
         r.arena_off = off;
         sl.reqs.push_back(r);
-        s->waiting.pop_front();
+        q.pop_front();
     }
     if (sl.reqs.empty()) return PICO_OK;
     std::stable_sort(sl.reqs.begin(), sl.reqs.end(),
@@ -194,9 +223,9 @@ int launch(pico_server *s, Slot &sl) {
     int rc = run_tasks_device(dev, T, algo, sl.ws, sl.ws_bytes, &s->cfg.tune, nullptr, sl.stream);
     if (rc) return rc;
     PICO_HIP_TRY(hipEventRecord(sl.done, sl.stream));
+    sl.cls = cls;
     sl.busy = true;
     ++s->launches;
-    s->launched_requests += T;
     return PICO_OK;
 }
 
@@ -218,7 +247,10 @@ int pico_server_create(const pico_server_config *cfg, pico_server **out) {
         return PICO_EINVAL;
     }
     if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_tasks_per_launch < 1 ||
-        (cfg->arena_bytes > 0 && !cfg->arena) || ((uintptr_t)cfg->arena & 255) != 0) {
+        cfg->max_large_slots < 0 || (cfg->arena_bytes > 0 && !cfg->arena) ||
+        ((uintptr_t)cfg->arena & 255) != 0 || cfg->tune.reserved != 0 || cfg->class_bounds[0] < 0 ||
+        cfg->class_bounds[1] < 0 ||
+        (cfg->class_bounds[0] > 0 && cfg->class_bounds[1] > 0 && cfg->class_bounds[1] < cfg->class_bounds[0])) {
         set_error("bad server configuration (max_inflight %d, max_tasks_per_launch %lld, arena %p)",
                   cfg->max_inflight, (long long)cfg->max_tasks_per_launch, cfg->arena);
         return PICO_EINVAL;
@@ -231,6 +263,10 @@ int pico_server_create(const pico_server_config *cfg, pico_server **out) {
         return PICO_ENOMEM;
     }
     s->cfg = *cfg;
+    s->bound[0] = cfg->class_bounds[0] > 0 ? cfg->class_bounds[0] : 16384;
+    s->bound[1] = cfg->class_bounds[1] > 0 ? cfg->class_bounds[1] : 131072;
+    if (s->bound[1] < s->bound[0]) s->bound[1] = s->bound[0];
+    s->max_large = cfg->max_large_slots > 0 ? cfg->max_large_slots : std::max(1, cfg->max_inflight / 2);
     (void)hipGetDevice(&s->device);
     s->arena.reset(cfg->arena_bytes);
     s->slots.resize((size_t)cfg->max_inflight);
@@ -269,12 +305,12 @@ int pico_server_submit(pico_server *s, const pico_request *req) {
     Req r;
     r.r = *req;
     r.bytes = task_scratch_bytes(req->n, req->m, s->cfg.algo);
-    if (r.bytes > s->arena.capacity()) {
+    if (Arena::granule(r.bytes) > s->arena.capacity()) {
         set_error("request needs %zu bytes of scratch, the arena holds %zu", r.bytes, s->arena.capacity());
         return PICO_ENOMEM;
     }
     r.t_submit = now_ns();
-    s->waiting.push_back(r);
+    s->waiting[class_of(s, req->n)].push_back(r);
     return PICO_OK;
 }
 
@@ -289,8 +325,12 @@ int pico_server_progress(pico_server *s, pico_completion *done, int max_done, in
     if (cur != s->device) PICO_HIP_TRY(hipSetDevice(s->device));
     int rc = reap(s);
     for (Slot &sl : s->slots) {
-        if (rc || s->waiting.empty()) break;
-        if (!sl.busy) rc = launch(s, sl);
+        if (rc) break;
+        if (sl.busy) continue;
+        const int c = pick_class(s);
+        if (c < 0) break;
+        rc = launch(s, sl, c);
+        if (!rc && !sl.busy) break;  // nothing fitted in the arena: wait for completions
     }
     if (cur != s->device) (void)hipSetDevice(cur);
     int k = 0;
@@ -313,7 +353,9 @@ int pico_server_query(const pico_server *s, pico_server_status *st) {
         inflight += (int64_t)sl.reqs.size();
         busy += sl.busy ? 1 : 0;
     }
-    st->waiting = (int64_t)s->waiting.size();
+    int64_t waiting = 0;
+    for (int c = 0; c < kClasses; ++c) waiting += (int64_t)s->waiting[c].size();
+    st->waiting = waiting;
     st->inflight = inflight;
     st->ready = (int64_t)s->ready.size();
     st->busy_slots = busy;

@@ -10,13 +10,13 @@ Usage (each run writes CSV files under its -d directory):
       python3 bench.py ... --copy-calibration    # bytes written per dispatch (KiB)
 
   python -m paper_2402_15253_amd.profiling stats DIR
-  python -m paper_2402_15253_amd.profiling traffic DIR_F DIR_W
+  python -m paper_2402_15253_amd.profiling traffic DIR_F DIR_W CONFIG
 
 The traffic summary scales each counter by what the same counter reads for
-the plain device-to-device copy that bench.py's --copy-calibration performs
-(a known number of bytes read and written), and reports per-launch bytes for
-the decomposition kernels.  It also records a hash of the HIP sources, so a
-reader can tell whether the kernels changed since the counters were taken.
+the 1 GiB device-to-device copy that bench.py's --copy-calibration performs
+(2^30 bytes read and 2^30 written), and reports per-launch bytes for the
+decomposition kernels.  Each kernel's line carries a hash of the sources it is
+built from; bench.py uses a traffic figure only while that hash still matches.
 """
 from __future__ import annotations
 
@@ -24,27 +24,33 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNELS = ("po_persistent", "hc_persistent")
-COPY_MARK = "copy"  # torch's copy kernel names contain this
+ROOT = os.path.dirname(HERE)
+KERNEL_SOURCES = {
+    "po_persistent": ("peelone.hip", "common.hpp"),
+    "hc_persistent": ("histocore.hip", "common.hpp"),
+    "batched_kernel": ("batched.hip", "common.hpp"),
+}
+KERNELS = tuple(KERNEL_SOURCES)
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 1 << 30
 
 
-def source_hash() -> str:
-    """Hash of the HIP sources and header the kernels are built from."""
+def source_hash(kernel: str) -> str:
+    """Hash of the HIP sources one kernel is built from."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*"))) + \
-        [os.path.join(HERE, "..", "include", "pico.h")]
-    for f in files:
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
-            h.update(fh.read())
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def _find(d: str, suffix: str) -> str:
-    hits = glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
     if not hits:
         raise FileNotFoundError(f"no *{suffix} under {d}")
     return hits[0]
@@ -55,67 +61,87 @@ def kernel_stats(d: str) -> dict:
     out = {}
     with open(_find(d, "kernel_stats.csv")) as f:
         for row in csv.DictReader(f):
-            name = row["Name"]
             for k in KERNELS:
-                if k in name:
+                if k in row["Name"]:
                     out[k] = (int(row["Calls"]), float(row["AverageNs"]) / 1e6,
                               float(row["TotalDurationNs"]) / 1e6)
     return out
 
 
-def _counter_rows(d: str, counter: str):
-    path = _find(d, "counter_collection.csv")
-    with open(path) as f:
-        for row in csv.DictReader(f):
-            if row.get("Counter_Name") == counter:
-                yield row["Kernel_Name"], float(row["Counter_Value"])
-
-
 def counter_per_dispatch(d: str, counter: str) -> dict:
-    """Mean counter value per dispatch, by kernel short name ('copy' for the
-    calibration copy, which is the largest copy dispatch of the run)."""
+    """Mean counter value (KiB) per dispatch of each decomposition kernel, and
+    the calibration copy's value ('copy': the largest copyBuffer dispatch)."""
     acc, copy_max = {}, 0.0
-    for name, val in _counter_rows(d, counter):
-        for k in KERNELS:
-            if k in name:
-                s, c = acc.get(k, (0.0, 0))
-                acc[k] = (s + val, c + 1)
-        if COPY_MARK in name.lower() or "elementwise" in name:
-            copy_max = max(copy_max, val)
+    with open(_find(d, "counter_collection.csv")) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name, val = row["Kernel_Name"], float(row["Counter_Value"])
+            for k in KERNELS:
+                if k in name:
+                    s, c = acc.get(k, (0.0, 0))
+                    acc[k] = (s + val, c + 1)
+            if COPY_KERNEL in name:
+                copy_max = max(copy_max, val)
     out = {k: s / c for k, (s, c) in acc.items()}
     out["copy"] = copy_max
     return out
 
 
-def traffic(dir_fetch: str, dir_write: str, copy_bytes: int) -> dict:
+def traffic(dir_fetch: str, dir_write: str) -> dict:
     """Per-launch HBM bytes read and written, scaled by the copy calibration."""
     fetch = counter_per_dispatch(dir_fetch, "FETCH_SIZE")
     write = counter_per_dispatch(dir_write, "WRITE_SIZE")
-    f_scale = copy_bytes / fetch["copy"] if fetch.get("copy") else None
-    w_scale = copy_bytes / write["copy"] if write.get("copy") else None
-    out = {"copy_bytes": copy_bytes, "fetch_factor": f_scale, "write_factor": w_scale}
+    f_scale = COPY_BYTES / fetch["copy"] if fetch.get("copy") else None
+    w_scale = COPY_BYTES / write["copy"] if write.get("copy") else None
+    out = {"fetch_factor": f_scale, "write_factor": w_scale,
+           "copy_fetch_kib": fetch.get("copy"), "copy_write_kib": write.get("copy")}
     for k in KERNELS:
         if k in fetch and k in write and f_scale and w_scale:
-            rd = fetch[k] * f_scale
-            wr = write[k] * w_scale
+            rd, wr = fetch[k] * f_scale, write[k] * w_scale
             out[k] = {"read_bytes": int(rd), "write_bytes": int(wr), "bytes": int(rd + wr),
-                      "fetch_kib_raw": fetch[k], "write_kib_raw": write[k]}
+                      "fetch_kib_raw": round(fetch[k], 1), "write_kib_raw": round(write[k], 1)}
     return out
+
+
+_LINE = re.compile(r"^traffic (\w+) (\w+) bytes_per_launch=(\d+) source=([0-9a-f]+)\s*$")
+
+
+def format_traffic(t: dict, config: str) -> str:
+    lines = [f"fetch_factor {t['fetch_factor']:.4f} (copy of 2^30 B read as "
+             f"{t['copy_fetch_kib']:.1f} KiB FETCH_SIZE)",
+             f"write_factor {t['write_factor']:.4f} (copy of 2^30 B written as "
+             f"{t['copy_write_kib']:.1f} KiB WRITE_SIZE)"]
+    for k in KERNELS:
+        if k in t:
+            v = t[k]
+            lines.append(f"{k}: read {v['read_bytes']} B, write {v['write_bytes']} B per launch "
+                         f"(raw FETCH_SIZE {v['fetch_kib_raw']} KiB, WRITE_SIZE {v['write_kib_raw']} KiB)")
+            lines.append(f"traffic {k} {config} bytes_per_launch={v['bytes']} source={source_hash(k)}")
+    return "\n".join(lines)
+
+
+def recorded_traffic(kernel: str, config: str) -> int | None:
+    """HBM bytes per launch of `kernel` on `config` from the committed
+    summaries under profiles/, if the kernel's sources are unchanged since."""
+    want = source_hash(kernel)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md")) +
+                       glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        with open(path) as f:
+            for line in f:
+                m = _LINE.match(line.strip())
+                if m and m.group(1) == kernel and m.group(2) == config and m.group(4) == want:
+                    return int(m.group(3))
+    return None
 
 
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
-        st = kernel_stats(argv[1])
-        print(f"source_hash: {source_hash()}")
-        for k, (calls, avg, tot) in st.items():
-            print(f"{k}: calls {calls} avg_ms {avg:.4f} total_ms {tot:.3f}")
+        for k, (calls, avg, tot) in kernel_stats(argv[1]).items():
+            print(f"{k}: calls {calls} avg_ms {avg:.4f} total_ms {tot:.3f} source={source_hash(k)}")
         return 0
-    if len(argv) >= 3 and argv[0] == "traffic":
-        copy_bytes = int(argv[3]) if len(argv) > 3 else 1 << 30
-        t = traffic(argv[1], argv[2], copy_bytes)
-        print(f"source_hash: {source_hash()}")
-        for k, v in t.items():
-            print(f"{k}: {v}")
+    if len(argv) >= 4 and argv[0] == "traffic":
+        print(format_traffic(traffic(argv[1], argv[2]), argv[3]))
         return 0
     print(__doc__)
     return 2

@@ -62,9 +62,10 @@ def test_tasks_match_oracle(pool, algo):
 @pytest.mark.parametrize("algo", ["peelone", "histocore"])
 def test_server_alone_vs_mix(pool, algo):
     """Requests arrive in bursts while earlier ones run; the arena admits only
-    part of them at a time, and up to three launches are in flight.  Each
-    result equals the graph's result alone (the plain single-graph call) and
-    the oracle's."""
+    part of them at a time, up to three launches are in flight, and small
+    class bounds spread the pool over all three size classes.  Each result
+    equals the graph's result alone (the plain single-graph call) and the
+    oracle's."""
     b, graphs = pool
     code = pico.ALGOS[algo]
     alone = []
@@ -80,7 +81,8 @@ def test_server_alone_vs_mix(pool, algo):
         assert np.array_equal(a, g["want"])
     need = [pico.pico_task_scratch_bytes(g["n"], g["m"], code) for g in graphs]
     arena = max(3 * max(need), 1 << 20)  # well below the sum over all requests
-    srv = pico.Server(algo, arena_bytes=arena, max_inflight=3, max_tasks_per_launch=16)
+    srv = pico.Server(algo, arena_bytes=arena, max_inflight=3, max_tasks_per_launch=16,
+                      class_bounds=(2000, 12000), max_large_slots=1)
     rng = np.random.default_rng(5)
     R = 300
     pick = rng.integers(0, len(graphs), R)
@@ -124,3 +126,13 @@ def test_server_rejects_what_never_fits(pool):
         srv.submit(g["off"], b.cols, g["n"], g["m"], out, 0)
     assert e.value.status == pico.PICO_ENOMEM
     srv.close()
+
+
+@pytest.mark.skip(reason="persistent request-queue kernel (a kernel polling a request ring in pinned "
+                         "host memory and writing completion words there) faulted the GPU twice "
+                         "on its first requests; switched off, see DESIGN.md")
+def test_persistent_queue_server_alone_vs_mix():
+    """Placeholder for the persistent-queue form of the server: the same
+    alone-versus-mix check as test_server_alone_vs_mix, with one kernel
+    instance taking requests from a host ring."""
+    raise AssertionError("persistent queue mode is switched off")
