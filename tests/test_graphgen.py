@@ -75,3 +75,52 @@ def test_g1_shape():
     g = gg.g1()
     assert g.degrees().tolist() == [1, 1, 2, 3, 2, 5]
     assert g.m == 14
+
+
+def test_pieces_below_the_32_bit_count_limit_give_the_same_csr():
+    """CSR construction splits its inputs and key ranges into pieces; the
+    result must not depend on the piece size."""
+    ref = gg.rmat(12, 16, 3)
+    old = gg._PIECE_MAX
+    try:
+        gg._PIECE_MAX = 3000
+        small = gg.rmat(12, 16, 3)
+    finally:
+        gg._PIECE_MAX = old
+    assert torch.equal(ref.offsets, small.offsets) and torch.equal(ref.cols, small.cols)
+
+
+def test_mixed_batch_structure():
+    b = gg.mixed_batch(24, 2, 5000, seed=31)
+    assert b.num_graphs == 24 and b.vptr[0] == 0 and b.offsets[0] == 0
+    assert int(b.offsets[-1]) == b.total_m
+    for g in range(b.num_graphs):
+        one = b.graph(g)
+        _check_csr(one)
+        assert one.n == int(b.vptr[g + 1] - b.vptr[g])
+        if one.m:
+            assert int(one.cols.max()) < one.n  # graph-local ids
+    sizes = (b.vptr[1:] - b.vptr[:-1])
+    assert int(sizes.min()) >= 2 and int(sizes.max()) <= 5000
+    # deterministic
+    assert torch.equal(gg.mixed_batch(24, 2, 5000, seed=31).cols, b.cols)
+
+
+def test_lognormal_sizes_and_poisson_trace_statistics():
+    s = gg.lognormal_sizes(20000, 20000, 1.5, 8_000_000, 2000).double()
+    med = float(s.median())
+    assert 18000 < med < 22000                       # median 20,000
+    z = torch.log(s[(s > 2) & (s < 8_000_000)] / 20000)
+    assert 1.4 < float(z.std()) < 1.6                # sigma 1.5
+    t, pick = gg.poisson_trace(2000.0, 20.0, 2048, seed=2000)
+    assert abs(t.numel() - 40000) < 4 * 200          # Poisson count, sd = 200
+    gaps = torch.diff(t)
+    assert (gaps > 0).all() and abs(float(gaps.mean()) - 1 / 2000) < 2e-5
+    assert int(pick.min()) >= 0 and int(pick.max()) < 2048
+
+
+def test_serving_pool_structure():
+    p = gg.serving_pool(6, 500, 1.0, 4000, seed=9)
+    assert p.num_graphs == 6
+    for g in range(6):
+        _check_csr(p.graph(g))
