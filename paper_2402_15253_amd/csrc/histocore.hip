@@ -49,10 +49,6 @@ constexpr int kSmall = 16;     // lane-serial work up to this many items
 constexpr int kLdsCap = 2048;  // InitHisto: LDS histogram per wave up to this degree
 constexpr int kInitCh = 1024;  // InitHisto: edges per heavy piece
 constexpr int kSumWave = 512;  // SumHisto: one wave up to this value, a workgroup above
-constexpr int kAggHub = 256;   // UpdateHisto: moves into neighbours of this degree or more are
-                               // combined per histogram bucket in LDS before the atomics
-constexpr int kAggSlots = 2048;
-constexpr int kAggProbe = 8;
 
 // Cumulative counters.  FET packs (edges << 31) | slots of the frontier lists.
 enum { FET = 0, H_TAIL, HS_TAIL, N_MOVES, N_EDGES, N_BUCKETS };
@@ -369,78 +365,6 @@ __device__ void sum_heavy(const HcArgs<Off> &a, const int32_t *F, const long lon
 
 // ---------------------------------------------------------------- UpdateHisto
 
-// Workgroup-local combining of histogram moves into high-degree neighbours.
-// Many frontier vertices of a round share a hub neighbour u and move their
-// count into the same few buckets of u's histogram (its top bucket, and the
-// small new values), so their atomics would serialise on a handful of
-// addresses.  Such moves are summed per bucket in an LDS table (open
-// addressing on the bucket's position) and applied once per workgroup at the
-// end of the phase.  A combined decrement of u's top bucket by c detects the
-// crossing exactly: the top bucket only falls during the phase, so the one
-// update that takes it from >= core[u] to < core[u] (old >= core[u] >
-// old - c) is unique, as the single-step test old == core[u] is.  Entries
-// for a top bucket carry u; plain entries carry -1.
-struct AggEntry {
-    unsigned long long pos;  // histogram position, or kAggEmpty
-    int delta;
-    int u;
-};
-constexpr unsigned long long kAggEmpty = ~0ull;
-
-__device__ __forceinline__ bool agg_add(AggEntry *T, long long pos, int delta, int u) {
-    const unsigned h = (unsigned)(((unsigned long long)pos * 0x9E3779B97F4A7C15ull) >> 53);
-#pragma unroll 1
-    for (int p = 0; p < kAggProbe; ++p) {
-        AggEntry &e = T[(h + p) & (kAggSlots - 1)];
-        const unsigned long long old = atomicCAS(&e.pos, kAggEmpty, (unsigned long long)pos);
-        if (old == kAggEmpty || old == (unsigned long long)pos) {
-            e.u = u;  // every adder of this position writes the same value
-            atomicAdd(&e.delta, delta);
-            return true;
-        }
-    }
-    return false;
-}
-
-__device__ __forceinline__ void agg_clear(AggEntry *T) {
-    for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
-        T[i].pos = kAggEmpty;
-        T[i].delta = 0;
-        T[i].u = -1;
-    }
-}
-
-// Apply the table (all threads, after a workgroup barrier) and clear it.
-template <typename Off>
-__device__ __forceinline__ void agg_flush(AggEntry *T, const HcArgs<Off> &a, int nxt,
-                                          unsigned long long fbase) {
-    GridState *gs = &a.st->g;
-#pragma unroll 1
-    for (int i0 = 0; i0 < kAggSlots; i0 += kBlock) {
-        AggEntry &e = T[i0 + threadIdx.x];
-        bool push = false;
-        int u = 0;
-        long long rs = 0, d = 0;
-        if (e.pos != kAggEmpty && e.delta != 0) {
-            if (e.u >= 0) {
-                u = e.u;
-                rs = (long long)a.off[u];
-                const long long cu = (long long)e.pos - rs + 1;
-                const int old = atomicAdd(&a.histo[e.pos], e.delta);
-                push = (long long)old >= cu && (long long)old + e.delta < cu;
-                if (push) d = (long long)a.off[u + 1] - rs;
-            } else {
-                atomicAdd(&a.histo[e.pos], e.delta);  // no return value needed
-            }
-        }
-        wave_push_packed(push, u, rs, d, &gs->ctr[FET].v, fbase, a.F[nxt], a.FE[nxt], a.FR[nxt]);
-        e.pos = kAggEmpty;
-        e.delta = 0;
-        e.u = -1;
-    }
-    __syncthreads();
-}
-
 // kEbR edges (v, u) of UpdateHisto per thread, all threads together: the
 // neighbour values, then the offsets of the neighbours that move, then the
 // histogram updates, each for all edges before any result is used.  A
@@ -449,8 +373,7 @@ template <typename Off>
 __device__ __forceinline__ void hc_relax(const bool (&act0)[kEbR], const int (&u)[kEbR],
                                          const int (&cv)[kEbR], const int (&ov)[kEbR],
                                          const int (&du)[kEbR], const HcArgs<Off> &a, int nxt,
-                                         unsigned long long fbase, long long &nmove,
-                                         AggEntry *agg) {
+                                         unsigned long long fbase, long long &nmove) {
     GridState *gs = &a.st->g;
     // A neighbour of degree <= cv has core[u] <= deg(u) <= cv: never moved.
     bool act[kEbR];
@@ -470,16 +393,6 @@ __device__ __forceinline__ void hc_relax(const bool (&act0)[kEbR], const int (&u
 #pragma unroll
     for (int r = 0; r < kEbR; ++r) {
         push[r] = false;
-        if (mv[r] && du[r] >= kAggHub) {
-            // hub neighbour: combine in LDS; fall back to direct atomics if the table is full
-            const bool top = ov[r] >= cu[r];
-            const long long pd = hb[r] + (top ? cu[r] : ov[r]);
-            if (agg_add(agg, pd, -1, top ? u[r] : -1)) {
-                if (!agg_add(agg, hb[r] + cv[r], 1, -1)) atomicAdd(&a.histo[hb[r] + cv[r]], 1);
-                ++nmove;
-                mv[r] = false;
-            }
-        }
         if (mv[r]) {
             if (ov[r] >= cu[r]) {
                 // v leaves u's top bucket: the only case whose old count matters
@@ -503,9 +416,7 @@ __device__ __forceinline__ void hc_relax(const bool (&act0)[kEbR], const int (&u
 
 template <typename Off>
 __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
-    __shared__ __attribute__((aligned(16))) int lds_all[kWavesPerBlock][kLdsCap];
-    static_assert(sizeof(AggEntry) * kAggSlots <= sizeof(int) * kWavesPerBlock * kLdsCap,
-                  "combining table must fit in the InitHisto LDS area");
+    __shared__ int lds_all[kWavesPerBlock][kLdsCap];
     __shared__ int part[kBlock];
     __shared__ int first_ok;
     __shared__ int lds_scan[kWavesPerBlock];
@@ -528,11 +439,6 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
     if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[0].v);
     init_histo<Off>(a, lds_all[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64);
-    // InitHisto is done with its LDS histograms: the area becomes the
-    // UpdateHisto combining table (cleared here, and by every flush)
-    AggEntry *agg = reinterpret_cast<AggEntry *>(&lds_all[0][0]);
-    __syncthreads();
-    agg_clear(agg);
     if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     const unsigned long long h_end = snap[H_TAIL], hs_end = snap[HS_TAIL];
     init_heavy<Off>(a, 0, h_end, 0);
@@ -576,10 +482,8 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
                               cvr[q] = L.p0[own[q]];
                               ovr[q] = L.p1[own[q]];
                           }
-                          hc_relax<Off>(act, u, cvr, ovr, du, a, nxt, fnext, nmove, agg);
+                          hc_relax<Off>(act, u, cvr, ovr, du, a, nxt, fnext, nmove);
                       });
-        __syncthreads();
-        agg_flush<Off>(agg, a, nxt, fnext);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[4].v);
         nf = (long long)((snap[FET] & kSlotMask) - fnext);
