@@ -182,7 +182,8 @@ def bench_batched(args, pico, torch, np):
     import graphgen as gg
     dev = "cuda:0"
     t0 = time.perf_counter()
-    b = gg.mixed_batch(count=args.graphs, device=dev)
+    b = gg.mixed_batch(count=args.graphs, device=dev,
+                       progress=lambda g: log(f"  generating graph {g} of {args.graphs}"))
     torch.cuda.synchronize()
     G, total_n, total_m = b.num_graphs, b.total_n, b.total_m
     log(f"batch {b.name}: G={G} total_n={total_n} total_m={total_m} "
@@ -319,7 +320,8 @@ def bench_serving(args, pico, torch, np):
     algo = args.algos.split(",")[0]
     code = pico.ALGOS[algo]
     t0 = time.perf_counter()
-    pool = gg.serving_pool(count=args.pool, device=dev)
+    pool = gg.serving_pool(count=args.pool, device=dev,
+                           progress=lambda g: log(f"  generating pool graph {g} of {args.pool}"))
     torch.cuda.synchronize()
     log(f"pool {pool.name}: total_n={pool.total_n} total_m={pool.total_m} "
         f"in {time.perf_counter() - t0:.1f}s")

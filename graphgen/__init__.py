@@ -549,17 +549,20 @@ def _rmat_local_pairs(n: int, ef: int, gs: int, device):
 
 
 def mixed_batch(count: int = 4096, lo: int = 200, hi: int = 200_000, seed: int = 4096,
-                device="cpu") -> GraphBatch:
+                device="cpu", progress=None) -> GraphBatch:
     """The batched workload: `count` graphs with vertex counts log-uniform on
     [lo, hi]; even-indexed graphs Erdos-Renyi G(n, M) with average degree
     uniform on [4, 32], odd-indexed R-MAT (scale ceil(log2 n), endpoints >= n
     redrawn) with edge factor uniform on [8, 16] and (0.57, 0.19, 0.19).
-    Graph g draws from streams seeded by (seed, g)."""
+    Graph g draws from streams seeded by (seed, g).  `progress(g)`, if
+    given, is called every 256 graphs."""
     sizes = batch_sizes(count, lo, hi, seed)
     u = uniform_u32(stream_seed(seed, 0x52), torch.arange(count)).to(torch.float64) / 2**32
     srcs, dsts = [], []
     vbase = 0
     for g in range(count):
+        if progress is not None and g % 256 == 0:
+            progress(g)
         n = int(sizes[g])
         gs = stream_seed(seed, g)
         if g % 2 == 0:
@@ -598,13 +601,15 @@ def lognormal_sizes(count: int, median: int, sigma: float, cap: int, seed: int,
 
 
 def serving_pool(count: int = 2048, median: int = 20_000, sigma: float = 1.5, cap: int = 8_000_000,
-                 edge_factor: int = 16, seed: int = 2000, device="cpu") -> GraphBatch:
+                 edge_factor: int = 16, seed: int = 2000, device="cpu", progress=None) -> GraphBatch:
     """The pool the serving trace draws from: `count` R-MAT graphs (edge factor
     16, (0.57, 0.19, 0.19)) with lognormal vertex counts (median 20,000,
     sigma 1.5, capped at 8,000,000), packed like a batch."""
     sizes = lognormal_sizes(count, median, sigma, cap, seed)
     srcs, dsts, vbase = [], [], 0
     for g in range(count):
+        if progress is not None and g % 256 == 0:
+            progress(g)
         n = int(sizes[g])
         s, t = _rmat_local_pairs(n, edge_factor, stream_seed(seed, 0x10000 + g), device)
         srcs.append(s + vbase)

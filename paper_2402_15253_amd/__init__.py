@@ -103,7 +103,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
                 ("max_tasks_per_launch", ctypes.c_int64), ("arena", ctypes.c_void_p),
                 ("arena_bytes", ctypes.c_size_t), ("tune", BatchTune),
-                ("class_bounds", ctypes.c_int64 * 2), ("max_large_slots", ctypes.c_int32),
+                ("class_bounds", ctypes.c_int64 * 2), ("giant_window", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -426,7 +426,7 @@ class Server:
 
     def __init__(self, algo="peelone", *, arena_bytes: int, max_inflight: int = 4,
                  max_tasks_per_launch: int = 4096, tune: BatchTune | None = None,
-                 class_bounds=(0, 0), max_large_slots: int = 0, device=None):
+                 class_bounds=(0, 0), giant_window: int = 0, device=None):
         lib = load_library()
         self._arena = torch.empty(max(arena_bytes, 256), dtype=torch.uint8, device=device or "cuda")
         cfg = ServerConfig()
@@ -437,7 +437,7 @@ class Server:
         cfg.arena_bytes = arena_bytes
         cfg.tune = tune if tune is not None else BatchTune()
         cfg.class_bounds[0], cfg.class_bounds[1] = class_bounds
-        cfg.max_large_slots = max_large_slots
+        cfg.giant_window = giant_window
         h = ctypes.c_void_p(0)
         torch.cuda.synchronize()
         _check(lib.pico_server_create(ctypes.byref(cfg), ctypes.byref(h)))

@@ -167,10 +167,6 @@ int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int a
     return PICO_OK;
 }
 
-size_t ws_bytes_for(int64_t n, int64_t m, int algo) {
-    return (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m)
-                                                         : histocore_ws_bytes(n, m);
-}
 
 int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo, int32_t *out,
              void *ws, size_t ws_bytes, pico_stats *st, hipStream_t s) {
@@ -208,6 +204,11 @@ __global__ void validate_kernel(const Off *__restrict__ off, const int32_t *__re
 }
 
 }  // namespace
+
+size_t ws_bytes_for(int64_t n, int64_t m, int algo) {
+    return (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m)
+                                                         : histocore_ws_bytes(n, m);
+}
 
 int check_device() {
     int dev = -1;

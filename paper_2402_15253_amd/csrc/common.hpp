@@ -548,9 +548,12 @@ void prof_end(int rec, hipStream_t s);
 size_t peelone_ws_bytes(int64_t n, int64_t m);
 size_t histocore_ws_bytes(int64_t n, int64_t m);
 
+// err_async (pinned host word) set: enqueue the kernel and a copy of its
+// error word there, and return without waiting; NULL: wait and report.
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
-                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream);
+                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream,
+                unsigned long long *err_async = nullptr);
 
 size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo);
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo);
@@ -559,6 +562,7 @@ pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T);
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
                      const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream);
 int check_device();
+size_t ws_bytes_for(int64_t n, int64_t m, int algo);
 
 
 int run_batched(const long long *vptr, const long long *off, const int32_t *cols, int64_t G,
@@ -568,7 +572,8 @@ int run_batched(const long long *vptr, const long long *off, const int32_t *cols
 
 template <typename Off>
 int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
-                  void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream);
+                  void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream,
+                  unsigned long long *err_async = nullptr);
 
 inline int grid_for(int64_t items_per_block_units, int cap) {
     int64_t g = items_per_block_units;

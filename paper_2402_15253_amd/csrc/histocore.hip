@@ -508,7 +508,7 @@ size_t histocore_ws_bytes(int64_t n, int64_t m) {
 
 template <typename Off>
 int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
-                  size_t ws_bytes, pico_stats *stats, hipStream_t stream) {
+                  size_t ws_bytes, pico_stats *stats, hipStream_t stream, unsigned long long *err_async) {
     if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
         set_error("m=%lld too large for the packed frontier counter", (long long)m);
         return PICO_ENOTSUP;
@@ -551,6 +551,11 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
     PICO_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(hc_persistent<Off>),
                                             dim3(blocks), dim3(kBlock), args, 0, stream));
     prof_end(rec, stream);
+    if (err_async) {  // the caller checks the error word once the stream is done
+        PICO_HIP_TRY(hipMemcpyAsync(err_async, &a.st->g.error.v, sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, stream));
+        return PICO_OK;
+    }
     HcState *h = static_cast<HcState *>(host_scratch(sizeof(HcState)));
     if (!h) return PICO_EHIP;
     PICO_HIP_TRY(hipMemcpyAsync(h, a.st, sizeof(HcState), hipMemcpyDeviceToHost, stream));
@@ -577,8 +582,8 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
 }
 
 template int run_histocore<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                    void *, size_t, pico_stats *, hipStream_t);
+                                    void *, size_t, pico_stats *, hipStream_t, unsigned long long *);
 template int run_histocore<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                    void *, size_t, pico_stats *, hipStream_t);
+                                    void *, size_t, pico_stats *, hipStream_t, unsigned long long *);
 
 }  // namespace pico

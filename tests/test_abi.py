@@ -85,6 +85,9 @@ def test_task_and_server_argument_checks_need_no_device():
     cfg.max_inflight, cfg.arena, cfg.arena_bytes = 2, 4096 + 8, 1 << 20  # misaligned arena
     assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
     cfg.arena = 4096
+    cfg.giant_window = -1
+    assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
+    cfg.giant_window = 0
     cfg.class_bounds[0], cfg.class_bounds[1] = 5000, 100  # bounds out of order
     assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
     assert ctypes.sizeof(pico.ServerConfig) == 4 + 4 + 8 + 8 + 8 + 16 + 16 + 4 + 4
