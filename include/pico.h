@@ -141,7 +141,10 @@ typedef struct pico_batch_tune {
     int32_t sum_wave_min;   /* HistoCore SumHisto: a vertex whose value exceeds this
                                scans its buckets with a whole wave, smaller ones with
                                one thread; 0 = default (64) */
-    int32_t reserved;       /* must be 0 */
+    int32_t help_min_vertices; /* PeelOne graphs with at least this many vertices (and
+                               values in global memory) are decomposed by their
+                               workgroup with the help of idle workgroups of the same
+                               launch; 0 = default (32768), -1 = never */
 } pico_batch_tune;
 
 /* Statistics of one batched call (filled only if requested; the call then
@@ -163,6 +166,8 @@ typedef struct pico_batch_stats {
     int64_t workgroups;      /* workgroups launched */
     int32_t lds_bytes;       /* dynamic LDS per workgroup used */
     int32_t blocks_per_cu;   /* resident workgroups per compute unit used */
+    int64_t helped_graphs;   /* graphs decomposed with their phases open to helpers */
+    int64_t help_chunks;     /* phase chunks run by helping workgroups */
 } pico_batch_stats;
 
 /*
@@ -255,16 +260,11 @@ PICO_API int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int 
  * (one HIP stream each, up to max_inflight launches in flight), so requests
  * that arrive while others run start on a free slot at once and overlap with
  * them on the device.  A launch holds requests of one size class only
- * (vertex counts below class_bounds[0], below class_bounds[1]), so small
- * requests never wait for a larger graph in their launch.  Larger requests
- * (PeelOne servers) run through the single-graph path -- the whole GPU per
- * graph -- in an exclusive window: while they wait no batched launch starts,
- * the slots drain, then up to giant_window of them run back to back, and
- * batched launches resume; windows and batched launches alternate.  A
- * HistoCore server launches its large requests in batched launches of their
- * own class.  The caller drives it: submit queues, progress reaps finished
- * launches and windows, launches what fits and returns completions.  Single
- * host thread per server.
+ * (vertex counts below class_bounds[0], below class_bounds[1], the rest), so
+ * small requests never wait for a large graph in their launch; large requests
+ * hold at most max_large_slots slots.  The caller drives it: submit queues,
+ * progress reaps finished launches, launches what fits and returns
+ * completions.  Single host thread per server.
  */
 typedef struct pico_server pico_server;
 
@@ -277,8 +277,8 @@ typedef struct pico_server_config {
     size_t arena_bytes;
     pico_batch_tune tune;          /* batched-kernel tuning (zeros / -1 = defaults) */
     int64_t class_bounds[2];       /* vertex-count bounds of the small and medium
-                                      classes; 0 = 16384 and 65536 */
-    int32_t giant_window;          /* large requests per exclusive window; 0 = 64 */
+                                      classes; 0 = 16384 and 131072 */
+    int32_t max_large_slots;       /* slots the large class may hold; 0 = half */
     int32_t reserved;              /* must be 0 */
 } pico_server_config;
 
@@ -292,7 +292,7 @@ typedef struct pico_request {
 
 typedef struct pico_completion {
     int64_t tag;
-    int32_t status;          /* PICO_OK, or PICO_EHIP if its kernel reported an error */
+    int32_t status;          /* PICO_OK */
     int32_t reserved;
     uint64_t t_submit_ns;    /* host steady-clock times: submit, launch, and */
     uint64_t t_launch_ns;    /* when progress saw the launch complete */
@@ -314,8 +314,7 @@ PICO_API int pico_server_submit(pico_server *server, const pico_request *req);
    *num_done gets the count.  Never blocks. */
 PICO_API int pico_server_progress(pico_server *server, pico_completion *done, int max_done,
                                   int *num_done);
-/* pico_server_query -- queue lengths, busy slots (and the window), launches
-   and windows so far, and arena use. */
+/* pico_server_query -- queue lengths, busy slots, launches so far and arena use. */
 PICO_API int pico_server_query(const pico_server *server, pico_server_status *status);
 /* pico_server_destroy -- wait for launches in flight, release everything the
    server allocated; requests still waiting are dropped. */

@@ -69,14 +69,15 @@ class PicoStats(ctypes.Structure):
 
 class BatchTune(ctypes.Structure):
     _fields_ = [("lds_bytes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("sum_wave_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sum_wave_min", ctypes.c_int32), ("help_min_vertices", ctypes.c_int32)]
 
-    def __init__(self, lds_bytes: int = -1, blocks_per_cu: int = 0, sum_wave_min: int = 0):
-        super().__init__(lds_bytes, blocks_per_cu, sum_wave_min, 0)
+    def __init__(self, lds_bytes: int = -1, blocks_per_cu: int = 0, sum_wave_min: int = 0,
+                 help_min_vertices: int = 0):
+        super().__init__(lds_bytes, blocks_per_cu, sum_wave_min, help_min_vertices)
 
     def as_dict(self) -> dict:
         return {"lds_bytes": self.lds_bytes, "blocks_per_cu": self.blocks_per_cu,
-                "sum_wave_min": self.sum_wave_min}
+                "sum_wave_min": self.sum_wave_min, "help_min_vertices": self.help_min_vertices}
 
 
 class BatchStats(ctypes.Structure):
@@ -85,7 +86,8 @@ class BatchStats(ctypes.Structure):
                 ("edges_scanned", ctypes.c_int64), ("buckets_scanned", ctypes.c_int64),
                 ("pushes", ctypes.c_int64), ("lds_graphs", ctypes.c_int64),
                 ("workgroups", ctypes.c_int64), ("lds_bytes", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("helped_graphs", ctypes.c_int64),
+                ("help_chunks", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -103,7 +105,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
                 ("max_tasks_per_launch", ctypes.c_int64), ("arena", ctypes.c_void_p),
                 ("arena_bytes", ctypes.c_size_t), ("tune", BatchTune),
-                ("class_bounds", ctypes.c_int64 * 2), ("giant_window", ctypes.c_int32),
+                ("class_bounds", ctypes.c_int64 * 2), ("max_large_slots", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -426,7 +428,7 @@ class Server:
 
     def __init__(self, algo="peelone", *, arena_bytes: int, max_inflight: int = 4,
                  max_tasks_per_launch: int = 4096, tune: BatchTune | None = None,
-                 class_bounds=(0, 0), giant_window: int = 0, device=None):
+                 class_bounds=(0, 0), max_large_slots: int = 0, device=None):
         lib = load_library()
         self._arena = torch.empty(max(arena_bytes, 256), dtype=torch.uint8, device=device or "cuda")
         cfg = ServerConfig()
@@ -437,7 +439,7 @@ class Server:
         cfg.arena_bytes = arena_bytes
         cfg.tune = tune if tune is not None else BatchTune()
         cfg.class_bounds[0], cfg.class_bounds[1] = class_bounds
-        cfg.giant_window = giant_window
+        cfg.max_large_slots = max_large_slots
         h = ctypes.c_void_p(0)
         torch.cuda.synchronize()
         _check(lib.pico_server_create(ctypes.byref(cfg), ctypes.byref(h)))

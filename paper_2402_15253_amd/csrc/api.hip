@@ -244,8 +244,8 @@ void prof_end(int rec, hipStream_t s) {
 using namespace pico;
 
 static bool tune_ok(const pico_batch_tune *tune) {
-    if (tune && tune->reserved != 0) {
-        set_error("pico_batch_tune.reserved must be 0");
+    if (tune && tune->help_min_vertices < -1) {
+        set_error("pico_batch_tune.help_min_vertices must be -1, 0 or positive");
         return false;
     }
     return true;
@@ -503,7 +503,9 @@ int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int algo,
     hipStream_t s = static_cast<hipStream_t>(stream);
     pico_task *dev = tasks_table(workspace, ws_bytes, num_tasks);
     PICO_HIP_TRY(hipMemcpyAsync(dev, tasks, sizeof(pico_task) * num_tasks, hipMemcpyHostToDevice, s));
-    rc = run_tasks_device(dev, num_tasks, a, workspace, ws_bytes, tune, stats, s);
+    int64_t max_n = 0;
+    for (int64_t i = 0; i < num_tasks; ++i) max_n = tasks[i].n > max_n ? tasks[i].n : max_n;
+    rc = run_tasks_device(dev, num_tasks, a, workspace, ws_bytes, tune, stats, s, max_n);
     if (rc) {
         g_prof.pending.clear();
         g_prof.used = 0;

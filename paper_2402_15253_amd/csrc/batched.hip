@@ -23,6 +23,7 @@
 // off[v] + b - 1 of the graph's histogram array) until no cnt falls below its
 // value.
 #include <climits>
+#include <cstddef>
 
 #include "common.hpp"
 
@@ -32,9 +33,64 @@ namespace {
 constexpr int kBatchRounds = 4;  // edges per thread per expansion step
 constexpr int kSumWaveMinDefault = 64;
 
+// ------------------------------------------------------------ helping
+//
+// A graph too large for one workgroup to finish quickly (PeelOne, values in
+// global memory, at least help_min vertices) is decomposed by the workgroup
+// that claimed it -- its leader -- with the help of workgroups that have no
+// graph left to claim.  The leader runs the level loop; each phase of it
+// (initialisation, a level's scan, a round of the level's drain) is a
+// parallel loop over an index range, cut into chunks.  For a phase worth
+// sharing the leader publishes it in its job record and lists the record on
+// an open board; any idle workgroup claims chunks with one compare-and-swap
+// on the record's packed (sequence, chunk count, next chunk) word, runs them
+// exactly as the leader would, and counts them done.  The leader takes
+// chunks too, then waits until every chunk is done and closes the phase.
+// Nobody waits for a workgroup that is not running: the leader waits only
+// for chunks already claimed by running helpers, and helpers wait for
+// nothing but new work (they leave once every graph of the launch is
+// finished).  Every wait is bounded.  Appends and the level minimum use
+// global counters in the job record.
+constexpr int kMaxGrid = 2048;        // workgroups per launch (job records)
+constexpr int kOpen = 64;             // board entries
+constexpr int kChunkItems = 1024;     // vertices / survivors per chunk
+constexpr int kChunkQueue = 256;      // queue entries per drain chunk
+constexpr int kHelpMinDefault = 32768;
+
+enum { PH_INIT = 0, PH_SCAN = 1, PH_DRAIN = 2 };
+
+struct alignas(128) JobCtl {
+    unsigned long long ctl;   // seq (16) | chunks (24) | next chunk (24); odd seq = open
+    unsigned long long done;  // chunks completed in the open phase
+};
+struct alignas(128) JobParams {
+    long long task, lo, hi;
+    int phase, k, cur, pad;
+};
+struct alignas(128) JobCnt {
+    unsigned a, b, c;
+    int mn;
+};
+struct Job {
+    JobCtl x;
+    JobParams p;
+    JobCnt n;
+};
+
+__host__ __device__ constexpr unsigned long long job_word(unsigned long long seq, unsigned long long nch,
+                                                          unsigned long long next) {
+    return (seq << 48) | (nch << 24) | next;
+}
+
 struct BatchState {
     Line next;  // graph claim counter
     Line levels, atomics, lds_graphs, frontier, edges, buckets, pushes, bad;
+    Line finished;  // graphs done (helpers leave when it reaches the graph count)
+    Line helped;    // graphs decomposed with the board open to helpers
+    Line helpchunks;
+    Line stuck;     // phases whose helpers did not finish within the wait bound
+    unsigned long long open[kOpen];  // board: job index + 1, or 0
+    Job jobs[kMaxGrid];
 };
 
 // One graph of a batch, as the kernel sees it.  `off` holds positions into
@@ -54,6 +110,8 @@ struct BatchArgs {
     int algo;
     int lds_cap;       // vertices whose values fit in dynamic LDS
     int sum_wave_min;  // SumHisto: larger values scan with a whole wave
+    int help_min;      // PeelOne graphs of at least this many vertices (global tier) take helpers; 0 = never
+    unsigned long long limit;  // bound on every wait (wall-clock ticks)
     BatchState *st;
 };
 
@@ -395,6 +453,297 @@ __device__ void histo_graph(const Task &t, int sum_wave_min, WgCounters &w, Expa
     __syncthreads();
 }
 
+// ------------------------------------------------ PeelOne with helpers
+
+// Wave-aggregated append to a list with a global counter.  Every lane of the
+// wave must call it.
+__device__ __forceinline__ void g_append(bool pred, int item, int32_t *list, unsigned *cnt) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned base = 0;
+    if (lane_id() == leader) base = atomicAdd(cnt, (unsigned)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) list[base + lane_rank(mask)] = item;
+}
+
+__device__ __forceinline__ void g_min(bool pred, int x, int *mn) {
+    const int m = wave_min(pred ? x : INT_MAX);
+    if (lane_id() == 0 && m != INT_MAX) atomicMin(mn, m);
+}
+
+// One chunk [c0, c1) of a phase of graph t, run by the whole workgroup.
+__device__ void run_chunk(const Task &t, const JobParams &p, JobCnt *n, long long c0, long long c1,
+                          ExpandLds &X, Counts &c) {
+    const long long *off = t.off;
+    int32_t *core = t.core;
+    const int k = p.k;
+    if (p.phase == PH_INIT) {
+        for (long long i = c0 + threadIdx.x; i - (long long)threadIdx.x < c1; i += kBlock) {
+            int d = 0;
+            const bool in = i < c1;
+            if (in) {
+                d = (int)(off[i + 1] - off[i]);
+                core[i] = d;
+                if (d == 0) t.out[i] = 0;
+            }
+            g_append(in && d > 0, (int)i, t.L0, &n->a);
+            g_min(in && d > 0, d, &n->mn);
+        }
+    } else if (p.phase == PH_SCAN) {
+        const int32_t *src = p.cur ? t.L1 : t.L0;
+        int32_t *dst = p.cur ? t.L0 : t.L1;
+        for (long long i = c0 + threadIdx.x; i - (long long)threadIdx.x < c1; i += kBlock) {
+            int v = -1, cv = -1;
+            if (i < c1) {
+                v = src[i];
+                cv = core[v];
+                if (cv == k) t.out[v] = k;
+            }
+            g_append(cv == k, v, t.L2, &n->c);
+            g_append(cv > k, v, dst, &n->b);
+            g_min(cv > k, cv, &n->mn);
+        }
+    } else {  // PH_DRAIN: expand queue entries [c0, c1)
+        for (long long base = c0; base < c1; base += kBlock) {
+            const long long i = base + threadIdx.x;
+            const int v = i < c1 ? t.L2[i] : -1;
+            long long rs = 0;
+            int d = 0;
+            if (v >= 0) {
+                rs = off[v];
+                d = (int)(off[v + 1] - rs);
+            }
+            c.edges += d;
+            block_expand<kBatchRounds>(
+                d, rs, 0, 0, t.cols, X,
+                [&](const bool (&act)[kBatchRounds], const int (&u)[kBatchRounds],
+                    const int (&)[kBatchRounds]) {
+                    int cu[kBatchRounds], old[kBatchRounds];
+#pragma unroll
+                    for (int r = 0; r < kBatchRounds; ++r) cu[r] = act[r] ? core[u[r]] : 0;
+#pragma unroll
+                    for (int r = 0; r < kBatchRounds; ++r) {
+                        old[r] = 0;
+                        if (act[r] && cu[r] > k) {
+                            old[r] = atomicSub(&core[u[r]], 1);
+                            ++c.atomics;
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < kBatchRounds; ++r) {
+                        const bool push = act[r] && cu[r] > k && old[r] == k + 1;
+                        if (push) {
+                            t.out[u[r]] = k;
+                            ++c.pushes;
+                        }
+                        g_append(push, u[r], t.L2, &n->c);
+                    }
+                });
+        }
+    }
+}
+
+struct LeadLds {
+    long long chunk;  // claimed chunk index, or -1
+    unsigned a, b, c;
+    int mn;
+    int err;
+};
+
+// Claim the next chunk of an open job whose control word reads x (thread 0).
+__device__ __forceinline__ long long claim_chunk(Job *job, unsigned long long x) {
+    while (true) {
+        const unsigned long long seq = x >> 48, nch = (x >> 24) & 0xffffffull, nx = x & 0xffffffull;
+        if ((seq & 1ull) == 0 || nx >= nch) return -1;
+        const unsigned long long y = atomicCAS(&job->x.ctl, x, x + 1);
+        if (y == x) return (long long)nx;
+        x = y;
+    }
+}
+
+// The leader runs phase p over `items` items in chunks of `chunk`, opening
+// it to helpers when there is more than one chunk and the board took the
+// job.  On return every chunk is done and the job's counters are in `sh`.
+__device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shared, JobParams p,
+                          long long items, long long chunk, LeadLds &sh, ExpandLds &X, Counts &c) {
+    const long long nch = (items + chunk - 1) / chunk;
+    const bool open = shared && nch > 1;
+    if (threadIdx.x == 0) {
+        job->p = p;
+        if (open) {
+            st_rlx(&job->x.done, 0ull);
+            // 16-bit sequence; 2^16 is even, so the parity survives the wrap
+            const unsigned long long seq = ((ld_rlx(&job->x.ctl) >> 48) + 1) & 0xffffull;  // odd: open
+            fence_release();  // parameters and counters before the control word
+            st_rel(&job->x.ctl, job_word(seq, (unsigned long long)nch, 0));
+        }
+    }
+    __syncthreads();
+    long long own = 0;
+    for (long long q = 0;; ++q) {
+        if (threadIdx.x == 0) sh.chunk = open ? claim_chunk(job, ld_rlx(&job->x.ctl)) : (q < nch ? q : -1);
+        __syncthreads();
+        const long long ci = sh.chunk;
+        __syncthreads();
+        if (ci < 0) break;
+        const long long c0 = p.lo + ci * chunk, c1 = c0 + chunk < p.hi ? c0 + chunk : p.hi;
+        run_chunk(t, p, &job->n, c0, c1, X, c);
+        ++own;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (open) {
+            fence_release();
+            unsigned long long d = atomicAdd(&job->x.done, (unsigned long long)own) + own;
+            const unsigned long long t0 = wall_clock64();
+            while (d < (unsigned long long)nch) {  // chunks still being run by helpers
+                if (wall_clock64() - t0 > a.limit) {
+                    sh.err = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                d = ld_acq(&job->x.done);
+            }
+            const unsigned long long seq = ((ld_rlx(&job->x.ctl) >> 48) + 1) & 0xffffull;  // even: closed
+            st_rel(&job->x.ctl, job_word(seq, 0, 0));
+            fence_acquire();
+        }
+        sh.a = ld_rlx(&job->n.a);
+        sh.b = ld_rlx(&job->n.b);
+        sh.c = ld_rlx(&job->n.c);
+        sh.mn = ld_rlx(&job->n.mn);
+    }
+    __syncthreads();
+}
+
+// PeelOne of a global-tier graph by its leader, phases shared with helpers.
+__device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long task, LeadLds &sh,
+                                  ExpandLds &X, Counts &c) {
+    Job *job = &a.st->jobs[blockIdx.x];
+    // list the job on the board (no helpers if the board is full)
+    if (threadIdx.x == 0) {
+        sh.err = 0;
+        sh.chunk = -1;
+        for (int q = 0; q < kOpen; ++q) {
+            const int s = (int)((blockIdx.x + q) % kOpen);
+            if (atomicCAS(&a.st->open[s], 0ull, (unsigned long long)blockIdx.x + 1) == 0ull) {
+                sh.chunk = s;
+                break;
+            }
+        }
+        st_rlx(&job->n.a, 0u);
+        st_rlx(&job->n.b, 0u);
+        st_rlx(&job->n.c, 0u);
+        st_rlx(&job->n.mn, INT_MAX);
+    }
+    __syncthreads();
+    const int slot = (int)sh.chunk;
+    const bool shared = slot >= 0;
+    __syncthreads();
+    JobParams p;
+    p.task = task;
+    p.pad = 0;
+    p.phase = PH_INIT;
+    p.k = 0;
+    p.cur = 0;
+    p.lo = 0;
+    p.hi = t.n;
+    run_phase(a, t, job, shared, p, t.n, kChunkItems, sh, X, c);
+    const int peelable = (int)sh.a;
+    int k = sh.mn, cur = 0, qtail = 0, na = peelable;
+    while (qtail < peelable && !sh.err) {
+        if (threadIdx.x == 0) {
+            st_rlx(&job->n.b, 0u);
+            st_rlx(&job->n.c, (unsigned)qtail);
+            st_rlx(&job->n.mn, INT_MAX);
+        }
+        p.phase = PH_SCAN;
+        p.k = k;
+        p.cur = cur;
+        p.lo = 0;
+        p.hi = na;
+        run_phase(a, t, job, shared, p, na, kChunkItems, sh, X, c);
+        const int hi0 = (int)sh.c;
+        na = (int)sh.b;
+        cur ^= 1;
+        if (hi0 == qtail) {  // empty level: jump to the smallest value left
+            k = sh.mn;
+            if (na == 0) break;
+            continue;
+        }
+        int lo = qtail, hi = hi0;
+        while (lo < hi && !sh.err) {
+            p.phase = PH_DRAIN;
+            p.lo = lo;
+            p.hi = hi;
+            run_phase(a, t, job, shared, p, hi - lo, kChunkQueue, sh, X, c);
+            lo = hi;
+            hi = (int)sh.c;
+        }
+        qtail = hi;
+        ++c.levels;
+        k += 1;
+    }
+    c.frontier += peelable;
+    if (threadIdx.x == 0) {
+        if (shared) st_rel(&a.st->open[slot], 0ull);
+        if (sh.err) atomicAdd(&a.st->stuck.v, 1ull);
+        atomicAdd(&a.st->helped.v, shared ? 1ull : 0ull);
+    }
+    __syncthreads();
+}
+
+// A workgroup with no graph left helps open jobs until every graph of the
+// launch is finished.
+__device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
+    __shared__ long long job_ix;
+    const unsigned long long t0 = wall_clock64();
+    unsigned nap = 1;
+    while (true) {
+        if (threadIdx.x == 0) {
+            sh.chunk = -1;
+            job_ix = -1;
+            for (int q = 0; q < kOpen && sh.chunk < 0; ++q) {
+                const unsigned long long w = ld_rlx(&a.st->open[(blockIdx.x + q) % kOpen]);
+                if (w == 0ull) continue;
+                Job *job = &a.st->jobs[w - 1];
+                const long long ci = claim_chunk(job, ld_rlx(&job->x.ctl));
+                if (ci >= 0) {
+                    sh.chunk = ci;
+                    job_ix = (long long)(w - 1);
+                }
+            }
+            if (sh.chunk >= 0) {
+                fence_acquire();  // the phase's parameters and what earlier phases wrote
+                nap = 1;
+            } else if ((long long)ld_acq(&a.st->finished.v) >= a.T || wall_clock64() - t0 > a.limit) {
+                job_ix = -2;  // every graph is done: leave
+            } else {
+                for (unsigned q = 0; q < nap; ++q) __builtin_amdgcn_s_sleep(8);
+                nap = nap < 32 ? nap * 2 : 32;
+            }
+        }
+        __syncthreads();
+        const long long jx = job_ix, ci = sh.chunk;
+        __syncthreads();
+        if (jx == -2) break;
+        if (ci < 0) continue;
+        Job *job = &a.st->jobs[jx];
+        const JobParams p = job->p;
+        const Task t = a.tasks[p.task];
+        const long long chunk = p.phase == PH_DRAIN ? kChunkQueue : kChunkItems;
+        const long long c0 = p.lo + ci * chunk, c1 = c0 + chunk < p.hi ? c0 + chunk : p.hi;
+        run_chunk(t, p, &job->n, c0, c1, X, c);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            fence_release();  // the chunk's writes before its count
+            atomicAdd(&job->x.done, 1ull);
+            atomicAdd(&a.st->helpchunks.v, 1ull);
+        }
+    }
+}
+
 // One graph, by the workgroup: LDS tier if its values fit.
 __device__ __forceinline__ void decompose(const Task &t, int algo, int lds_cap, int sum_wave_min,
                                           WgCounters &w, ExpandLds &X, Counts &c) {
@@ -413,6 +762,7 @@ __device__ __forceinline__ void decompose(const Task &t, int algo, int lds_cap, 
 __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
     __shared__ WgCounters w;
     __shared__ ExpandLds X;
+    __shared__ LeadLds sh;
     __shared__ long long claim;
     Counts c;
     while (true) {
@@ -422,8 +772,14 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
         __syncthreads();
         if (j >= a.T) break;
         const Task t = a.tasks[j];
-        decompose(t, a.algo, a.lds_cap, a.sum_wave_min, w, X, c);
+        if (a.help_min > 0 && a.algo == PICO_ALGO_PEELONE && t.n > a.lds_cap && t.n >= a.help_min)
+            peel_graph_helped(a, t, j, sh, X, c);
+        else
+            decompose(t, a.algo, a.lds_cap, a.sum_wave_min, w, X, c);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&a.st->finished.v, 1ull);
     }
+    if (a.help_min > 0 && a.algo == PICO_ALGO_PEELONE) help(a, sh, X, c);
     // per-thread counts: atomics, edges, buckets, pushes; per-workgroup
     // (uniform, thread 0's): levels, frontier, lds graphs
     const long long s_atom = wave_sum64(c.atomics), s_edges = wave_sum64(c.edges);
@@ -536,17 +892,29 @@ int launch_config(const void *kernel, const pico_batch_tune *tune, long long T, 
     return PICO_OK;
 }
 
+int help_min_of(const pico_batch_tune *tune) {
+    if (!tune || tune->help_min_vertices == 0) return kHelpMinDefault;
+    return tune->help_min_vertices < 0 ? 0 : tune->help_min_vertices;
+}
+
+// big_task: some task may take helpers (then the grid is full even for few
+// tasks, so that idle workgroups exist to help).
 int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune *tune,
-                 BatchState *st, pico_batch_stats *stats, hipStream_t stream) {
+                 BatchState *st, pico_batch_stats *stats, hipStream_t stream, bool big_task) {
     Launch L;
-    int rc = launch_config(reinterpret_cast<const void *>(batched_kernel), tune, T, &L);
+    const int help_min = algo == PICO_ALGO_PEELONE ? help_min_of(tune) : 0;
+    const bool full = help_min > 0 && big_task;
+    int rc = launch_config(reinterpret_cast<const void *>(batched_kernel), tune, full ? (1ll << 40) : T, &L);
     if (rc) return rc;
+    if (L.blocks > kMaxGrid) L.blocks = kMaxGrid;
     BatchArgs a;
     a.tasks = tasks;
     a.T = T;
     a.algo = algo;
     a.lds_cap = L.lds_bytes / 4;
     a.sum_wave_min = tune && tune->sum_wave_min > 0 ? tune->sum_wave_min : kSumWaveMinDefault;
+    a.help_min = help_min;
+    a.limit = wall_ticks(60.0);
     a.st = st;
     int rec = prof_begin("batched_kernel", stream);
     hipLaunchKernelGGL(batched_kernel, dim3((unsigned)L.blocks), dim3(kBlock), L.lds_bytes, stream, a);
@@ -555,7 +923,8 @@ int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune
     if (stats) {
         BatchState *h = static_cast<BatchState *>(host_scratch(sizeof(BatchState)));
         if (!h) return PICO_EHIP;
-        PICO_HIP_TRY(hipMemcpyAsync(h, st, sizeof(BatchState), hipMemcpyDeviceToHost, stream));
+        // the counters only, not the job board
+        PICO_HIP_TRY(hipMemcpyAsync(h, st, offsetof(BatchState, open), hipMemcpyDeviceToHost, stream));
         PICO_HIP_TRY(hipStreamSynchronize(stream));
         stats->graphs = T;
         stats->iterations = (int64_t)h->levels.v;
@@ -568,6 +937,12 @@ int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune
         stats->workgroups = L.blocks;
         stats->lds_bytes = L.lds_bytes;
         stats->blocks_per_cu = L.blocks_per_cu;
+        stats->helped_graphs = (int64_t)h->helped.v;
+        stats->help_chunks = (int64_t)h->helpchunks.v;
+        if (h->stuck.v) {
+            set_error("%llu helped phases did not finish within the wait bound", (unsigned long long)h->stuck.v);
+            return PICO_EHIP;
+        }
         if (h->bad.v) {
             set_error("%llu graphs of the batch have a vertex count outside [0, 2^31)",
                       (unsigned long long)h->bad.v);
@@ -631,11 +1006,12 @@ int run_batched(const long long *vptr, const long long *off, const int32_t *cols
     PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st);
     PICO_LAUNCH("packed_tasks", packed_tasks, dim3((unsigned)((G + 255) / 256)), dim3(256), stream, p,
                 tasks, st);
-    return launch_tasks(tasks, G, algo, tune, st, stats, stream);
+    return launch_tasks(tasks, G, algo, tune, st, stats, stream, true);
 }
 
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
-                     const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream) {
+                     const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream,
+                     int64_t max_n) {
     Carve cv{static_cast<char *>(ws), 0, ws_bytes};
     Task *tasks = cv.take<Task>(T);
     cv.take<pico_task>(T);
@@ -647,7 +1023,8 @@ int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, 
     PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st);
     PICO_LAUNCH("public_tasks", public_tasks, dim3((unsigned)((T + 255) / 256)), dim3(256), stream,
                 dev_tasks, (long long)T, algo == PICO_ALGO_HISTOCORE ? 1 : 0, tasks);
-    return launch_tasks(tasks, T, algo, tune, st, stats, stream);
+    const int hm = help_min_of(tune);
+    return launch_tasks(tasks, T, algo, tune, st, stats, stream, hm > 0 && max_n >= hm);
 }
 
 // Device copy of a host task array inside the tasks workspace (second slot).

@@ -322,14 +322,15 @@ __device__ __forceinline__ void block_expand(int d, long long e0, int p0, int p1
 // whatever the row lengths; each step loads the entries covering the next
 // kBlock * R edges into LDS and locates every edge's entry by binary search.
 
-constexpr int kEbR = 4;                   // edges per thread per step
+constexpr int kEbR = 8;                   // edges per thread per step
 constexpr int kEbWin = kBlock * kEbR;     // edges per step
+constexpr int kEbEnt = 1024;              // frontier entries per LDS window
 struct EbLds {
-    int id[kEbWin + 1];
-    long long es[kEbWin + 1];
-    long long rs[kEbWin + 1];
-    int p0[kEbWin + 1];
-    int p1[kEbWin + 1];
+    int id[kEbEnt + 1];
+    long long es[kEbEnt + 1];  // es[w]: start of the first entry past the window
+    long long rs[kEbEnt + 1];
+    int p0[kEbEnt + 1];
+    int p1[kEbEnt + 1];
     long long next;
 };
 
@@ -373,18 +374,26 @@ __device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
     }
     __syncthreads();
     long long i0 = L.next;
-    for (long long s0 = lo; s0 < hi; s0 += kEbWin) {
-        const long long we = s0 + kEbWin < hi ? s0 + kEbWin : hi;
-        const int w = (int)(q1 - i0 < (long long)(kEbWin + 1) ? q1 - i0 : (long long)(kEbWin + 1));
-        for (int j = threadIdx.x; j < w; j += kBlock) {
+    for (long long s0 = lo; s0 < hi;) {
+        // the window: up to kEbEnt entries from the one holding s0, and the
+        // start of the entry after them, which bounds the edges this step
+        // may take (every entry holds at least one edge, so it lies past s0)
+        const int w = (int)(q1 - i0 < (long long)kEbEnt ? q1 - i0 : (long long)kEbEnt);
+        for (int j = threadIdx.x; j <= w; j += kBlock) {
             long long i = i0 + j;
-            L.id[j] = ids[i];
-            L.es[j] = es[i];
-            L.rs[j] = rs[i];
-            L.p0[j] = P0 ? P0[i] : 0;
-            L.p1[j] = P1 ? P1[i] : 0;
+            if (j < w) {
+                L.id[j] = ids[i];
+                L.es[j] = es[i];
+                L.rs[j] = rs[i];
+                L.p0[j] = P0 ? P0[i] : 0;
+                L.p1[j] = P1 ? P1[i] : 0;
+            } else {
+                L.es[j] = i < q1 ? es[i] : LLONG_MAX;
+            }
         }
         __syncthreads();
+        long long we = s0 + kEbWin < hi ? s0 + kEbWin : hi;
+        if (L.es[w] < we) we = L.es[w];
         bool act[kEbR];
         int u[kEbR], own[kEbR], ax[kEbR];
 #pragma unroll
@@ -399,9 +408,10 @@ __device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
         }
         f(act, u, own, L, ax);
         __syncthreads();
-        if (threadIdx.x == 0 && we < hi) L.next = i0 + lds_owner(L.es, w, we);
+        if (threadIdx.x == 0 && we < hi) L.next = i0 + lds_owner(L.es, w + 1, we);
         __syncthreads();
         i0 = L.next;
+        s0 = we;
     }
 }
 
@@ -559,8 +569,11 @@ size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo);
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo);
 size_t tasks_ws_bytes(int64_t T);
 pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T);
+// max_n: the largest vertex count among the tasks (decides whether the grid
+// is filled for helpers).
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
-                     const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream);
+                     const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream,
+                     int64_t max_n);
 int check_device();
 size_t ws_bytes_for(int64_t n, int64_t m, int algo);
 

@@ -2,30 +2,25 @@
 //
 // Requests name a device-resident CSR graph and a device output.  A request
 // is admitted when its per-request scratch (the decomposition's working
-// arrays) fits in the HBM arena the caller hands over.
+// arrays) fits in the HBM arena the caller hands over.  Admitted requests are
+// launched together, largest first, as one batched-kernel call on a free
+// launch slot (each slot its own stream), and a slot is reused as soon as its
+// launch has completed, so requests that arrive while others run are launched
+// on a free slot right away and their work overlaps on the device with the
+// launches already in flight.
 //
-// Small and medium requests (by vertex count) are launched together, largest
-// first, as one batched-kernel call on a free launch slot (each slot its own
-// stream; a workgroup per graph), and a slot is reused as soon as its launch
-// has completed, so requests that arrive while others run are launched on a
-// free slot right away and overlap on the device with the launches in
-// flight.  A launch holds requests of one class only and completes with its
-// slowest graph, so a small request never waits for a medium graph.
-//
-// Large requests would hold a workgroup -- and their launch -- for a long
-// time; they run instead through the single-graph path (the persistent
-// cooperative kernels, the whole GPU per graph) in an exclusive window: when
-// large requests are waiting, no new batched launch starts, the slots drain,
-// and then the waiting large requests (up to giant_window of them) are run
-// back to back on the window's stream; batched launches resume when the
-// window completes.  A cooperative kernel therefore never shares the device
-// with a batched kernel, and windows alternate with batched launches so
-// neither side starves.
+// A launch completes only with its slowest graph, so requests are kept in
+// three size classes (by vertex count) and a launch takes requests of one
+// class only: a small request never waits for a large graph of the same
+// launch.  Large requests may hold at most max_large_slots slots at a time,
+// so the small and medium classes always find a slot.  Among the classes
+// allowed on a free slot, the one whose oldest request has waited longest
+// goes first.
 //
 // The server is driven by the caller: pico_server_submit queues a request,
-// pico_server_progress reaps finished launches and windows (completion is an
-// event per slot / window), launches what fits, and hands back completions.
-// Nothing here blocks except pico_server_destroy.
+// pico_server_progress reaps finished launches (completion is an event per
+// slot), launches what fits, and hands back completions.  Nothing here blocks
+// except pico_server_destroy.
 #include <algorithm>
 #include <chrono>
 #include <climits>
@@ -122,19 +117,12 @@ struct pico_server {
     pico_server_config cfg;
     int device = 0;
     int64_t bound[2] = {0, 0};  // vertex-count bounds of the small and medium classes
-    int giant_window = 64;
+    int max_large = 1;
     pico::Arena arena;
-    std::deque<pico::Req> waiting[pico::kClasses];  // [2]: large requests for the window
+    std::deque<pico::Req> waiting[pico::kClasses];
     std::deque<pico_completion> ready;
     std::vector<pico::Slot> slots;
-    // exclusive window of large requests
-    hipStream_t gstream = nullptr;
-    hipEvent_t gdone = nullptr;
-    unsigned long long *gerr = nullptr;  // pinned: one error word per request of the window
-    std::vector<pico::Req> gw;
-    bool grunning = false;
-    bool batched_turn = false;  // after a window, batched launches go first
-    int64_t launches = 0, windows = 0, completed = 0;
+    int64_t launches = 0, completed = 0;
 };
 
 namespace pico {
@@ -143,13 +131,6 @@ namespace {
 int class_of(const pico_server *s, int64_t n) { return n < s->bound[0] ? 0 : n < s->bound[1] ? 1 : 2; }
 
 void destroy_slots(pico_server *s) {
-    if (s->gstream) (void)hipStreamSynchronize(s->gstream);
-    if (s->gdone) (void)hipEventDestroy(s->gdone);
-    if (s->gstream) (void)hipStreamDestroy(s->gstream);
-    if (s->gerr) (void)hipHostFree(s->gerr);
-    s->gstream = nullptr;
-    s->gdone = nullptr;
-    s->gerr = nullptr;
     for (Slot &sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
@@ -188,20 +169,16 @@ int reap(pico_server *s) {
     return PICO_OK;
 }
 
-// Large requests take the exclusive window with PeelOne only: the
-// single-graph HistoCore kernel indexes its histogram by CSR position and so
-// needs offsets starting at 0, which a request's rows need not.  A HistoCore
-// server launches its large requests in batched launches of their own class.
-bool uses_window(const pico_server *s) { return (s->cfg.algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE; }
-
-// The class a free slot serves next: the batched class whose oldest waiting
+// The class a free slot serves next: the allowed class whose oldest waiting
 // request was submitted first, or -1.
 int pick_class(const pico_server *s) {
+    int large_busy = 0;
+    for (const Slot &sl : s->slots) large_busy += (sl.busy && sl.cls == 2) ? 1 : 0;
     int best = -1;
     uint64_t t_best = 0;
-    const int nc = uses_window(s) ? 2 : kClasses;
-    for (int c = 0; c < nc; ++c) {
+    for (int c = 0; c < kClasses; ++c) {
         if (s->waiting[c].empty()) continue;
+        if (c == 2 && large_busy >= s->max_large) continue;
         const uint64_t t = s->waiting[c].front().t_submit;
         if (best < 0 || t < t_best) {
             best = c;
@@ -209,70 +186,6 @@ int pick_class(const pico_server *s) {
         }
     }
     return best;
-}
-
-int reap_window(pico_server *s) {
-    if (!s->grunning) return PICO_OK;
-    const hipError_t q = hipEventQuery(s->gdone);
-    if (q == hipErrorNotReady) return PICO_OK;
-    if (q != hipSuccess) {
-        set_error("large-request window failed: %s", hipGetErrorString(q));
-        return PICO_EHIP;
-    }
-    const uint64_t t = now_ns();
-    for (size_t i = 0; i < s->gw.size(); ++i) {
-        Req &r = s->gw[i];
-        s->arena.release(r.arena_off, r.bytes);
-        pico_completion c;
-        c.tag = r.r.tag;
-        c.status = s->gerr[i] ? PICO_EHIP : PICO_OK;
-        c.reserved = 0;
-        c.t_submit_ns = r.t_submit;
-        c.t_launch_ns = r.t_launch;
-        c.t_done_ns = t;
-        s->ready.push_back(c);
-        ++s->completed;
-    }
-    s->gw.clear();
-    s->grunning = false;
-    s->batched_turn = true;
-    return PICO_OK;
-}
-
-// Run the waiting large requests (up to giant_window, as the arena allows)
-// back to back on the window stream.  Called only with every slot idle.
-int launch_window(pico_server *s) {
-    char *base = static_cast<char *>(s->cfg.arena);
-    std::deque<Req> &q = s->waiting[2];
-    const int algo = (s->cfg.algo & PICO_ALGO_MASK) | PICO_OFFSETS_I64;
-    while (!q.empty() && (int)s->gw.size() < s->giant_window) {
-        Req &r = q.front();
-        const size_t need = ws_bytes_for(r.r.n, r.r.m, algo);
-        size_t off = 0;
-        if (!s->arena.alloc(need, &off)) break;
-        r.bytes = need;
-        r.arena_off = off;
-        r.t_launch = now_ns();
-        const size_t i = s->gw.size();
-        s->gerr[i] = 0;
-        int rc = r.r.n == 0 ? PICO_OK
-                 : (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE
-                     ? run_peelone<int64_t>(r.r.offsets, r.r.cols, r.r.n, r.r.m, r.r.out_core, base + off,
-                                            need, nullptr, s->gstream, &s->gerr[i])
-                     : run_histocore<int64_t>(r.r.offsets, r.r.cols, r.r.n, r.r.m, r.r.out_core,
-                                              base + off, need, nullptr, s->gstream, &s->gerr[i]);
-        if (rc) {
-            s->arena.release(off, need);
-            return rc;
-        }
-        s->gw.push_back(r);
-        q.pop_front();
-    }
-    if (s->gw.empty()) return PICO_OK;
-    PICO_HIP_TRY(hipEventRecord(s->gdone, s->gstream));
-    s->grunning = true;
-    ++s->windows;
-    return PICO_OK;
 }
 
 int launch(pico_server *s, Slot &sl, int cls) {
@@ -307,7 +220,8 @@ int launch(pico_server *s, Slot &sl, int cls) {
     pico_task *dev = tasks_table(sl.ws, sl.ws_bytes, T);
     PICO_HIP_TRY(hipMemcpyAsync(dev, sl.staging, sizeof(pico_task) * T, hipMemcpyHostToDevice, sl.stream));
     const int algo = s->cfg.algo & PICO_ALGO_MASK;
-    int rc = run_tasks_device(dev, T, algo, sl.ws, sl.ws_bytes, &s->cfg.tune, nullptr, sl.stream);
+    int rc = run_tasks_device(dev, T, algo, sl.ws, sl.ws_bytes, &s->cfg.tune, nullptr, sl.stream,
+                              sl.reqs.front().r.n);  // largest first
     if (rc) return rc;
     PICO_HIP_TRY(hipEventRecord(sl.done, sl.stream));
     sl.cls = cls;
@@ -334,8 +248,8 @@ int pico_server_create(const pico_server_config *cfg, pico_server **out) {
         return PICO_EINVAL;
     }
     if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_tasks_per_launch < 1 ||
-        cfg->giant_window < 0 || cfg->giant_window > 4096 || (cfg->arena_bytes > 0 && !cfg->arena) ||
-        ((uintptr_t)cfg->arena & 255) != 0 || cfg->tune.reserved != 0 || cfg->class_bounds[0] < 0 ||
+        cfg->max_large_slots < 0 || (cfg->arena_bytes > 0 && !cfg->arena) ||
+        ((uintptr_t)cfg->arena & 255) != 0 || cfg->tune.help_min_vertices < -1 || cfg->class_bounds[0] < 0 ||
         cfg->class_bounds[1] < 0 ||
         (cfg->class_bounds[0] > 0 && cfg->class_bounds[1] > 0 && cfg->class_bounds[1] < cfg->class_bounds[0])) {
         set_error("bad server configuration (max_inflight %d, max_tasks_per_launch %lld, arena %p)",
@@ -351,9 +265,9 @@ int pico_server_create(const pico_server_config *cfg, pico_server **out) {
     }
     s->cfg = *cfg;
     s->bound[0] = cfg->class_bounds[0] > 0 ? cfg->class_bounds[0] : 16384;
-    s->bound[1] = cfg->class_bounds[1] > 0 ? cfg->class_bounds[1] : 65536;
+    s->bound[1] = cfg->class_bounds[1] > 0 ? cfg->class_bounds[1] : 131072;
     if (s->bound[1] < s->bound[0]) s->bound[1] = s->bound[0];
-    s->giant_window = cfg->giant_window > 0 ? cfg->giant_window : 64;
+    s->max_large = cfg->max_large_slots > 0 ? cfg->max_large_slots : std::max(1, cfg->max_inflight / 2);
     (void)hipGetDevice(&s->device);
     s->arena.reset(cfg->arena_bytes);
     s->slots.resize((size_t)cfg->max_inflight);
@@ -368,11 +282,6 @@ int pico_server_create(const pico_server_config *cfg, pico_server **out) {
             break;
         if ((e = hipMalloc(&sl.ws, sl.ws_bytes)) != hipSuccess) break;
     }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->gdone, hipEventDisableTiming);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&s->gerr, sizeof(unsigned long long) * (size_t)s->giant_window,
-                          hipHostMallocDefault);
     if (e != hipSuccess) {
         set_error("server set-up failed: %s", hipGetErrorString(e));
         destroy_slots(s);
@@ -396,16 +305,13 @@ int pico_server_submit(pico_server *s, const pico_request *req) {
     }
     Req r;
     r.r = *req;
-    const int cls = class_of(s, req->n);
-    r.bytes = cls == 2 && uses_window(s)
-                  ? ws_bytes_for(req->n, req->m, (s->cfg.algo & PICO_ALGO_MASK) | PICO_OFFSETS_I64)
-                  : task_scratch_bytes(req->n, req->m, s->cfg.algo);
+    r.bytes = task_scratch_bytes(req->n, req->m, s->cfg.algo);
     if (Arena::granule(r.bytes) > s->arena.capacity()) {
         set_error("request needs %zu bytes of scratch, the arena holds %zu", r.bytes, s->arena.capacity());
         return PICO_ENOMEM;
     }
     r.t_submit = now_ns();
-    s->waiting[cls].push_back(r);
+    s->waiting[class_of(s, req->n)].push_back(r);
     return PICO_OK;
 }
 
@@ -419,23 +325,13 @@ int pico_server_progress(pico_server *s, pico_completion *done, int max_done, in
     (void)hipGetDevice(&cur);
     if (cur != s->device) PICO_HIP_TRY(hipSetDevice(s->device));
     int rc = reap(s);
-    if (!rc) rc = reap_window(s);
-    bool any_busy = false;
-    for (const Slot &sl : s->slots) any_busy = any_busy || sl.busy;
-    const bool giants = uses_window(s) && !s->waiting[2].empty();
-    if (!rc && !s->grunning && giants && !any_busy && !s->batched_turn) {
-        rc = launch_window(s);  // the device is free of batched kernels
-    } else if (!rc && !s->grunning && !(giants && !s->batched_turn)) {
-        // batched launches (held while large requests wait for the device to drain)
-        for (Slot &sl : s->slots) {
-            if (rc) break;
-            if (sl.busy) continue;
-            const int c = pick_class(s);
-            if (c < 0) break;
-            rc = launch(s, sl, c);
-            if (!rc && !sl.busy) break;  // nothing fitted in the arena: wait for completions
-        }
-        s->batched_turn = false;
+    for (Slot &sl : s->slots) {
+        if (rc) break;
+        if (sl.busy) continue;
+        const int c = pick_class(s);
+        if (c < 0) break;
+        rc = launch(s, sl, c);
+        if (!rc && !sl.busy) break;  // nothing fitted in the arena: wait for completions
     }
     if (cur != s->device) (void)hipSetDevice(cur);
     int k = 0;
@@ -453,7 +349,7 @@ int pico_server_query(const pico_server *s, pico_server_status *st) {
         set_error("NULL argument to pico_server_query");
         return PICO_EINVAL;
     }
-    int64_t inflight = (int64_t)s->gw.size(), busy = s->grunning ? 1 : 0;
+    int64_t inflight = 0, busy = 0;
     for (const Slot &sl : s->slots) {
         inflight += (int64_t)sl.reqs.size();
         busy += sl.busy ? 1 : 0;
@@ -464,7 +360,7 @@ int pico_server_query(const pico_server *s, pico_server_status *st) {
     st->inflight = inflight;
     st->ready = (int64_t)s->ready.size();
     st->busy_slots = busy;
-    st->launches = s->launches + s->windows;
+    st->launches = s->launches;
     st->completed = s->completed;
     st->arena_used = (int64_t)s->arena.used();
     st->arena_bytes = (int64_t)s->arena.capacity();

@@ -64,7 +64,7 @@ def test_task_and_server_argument_checks_need_no_device():
         pico.pico_task_scratch_bytes(2**31, 0, pe)
     assert pico.pico_tasks_workspace_bytes(100) > 100 * ctypes.sizeof(pico.Task)
     assert ctypes.sizeof(pico.Task) == 56 and ctypes.sizeof(pico.BatchTune) == 16
-    assert ctypes.sizeof(pico.BatchStats) == 9 * 8 + 8
+    assert ctypes.sizeof(pico.BatchStats) == 9 * 8 + 8 + 2 * 8
     assert ctypes.sizeof(pico.Completion) == 40
     # bad task lists are rejected on the host, before any device work
     bad = pico.Task(None, None, -1, 0, None, None, 0)
@@ -74,7 +74,7 @@ def test_task_and_server_argument_checks_need_no_device():
     assert pico.pico_coreness_tasks([short], pe, None, None, 0) == pico.PICO_ENOMEM
     assert pico.pico_coreness_tasks([], pe, None, None, 0) == pico.PICO_OK
     tune = pico.BatchTune()
-    tune.reserved = 1
+    tune.help_min_vertices = -5
     assert pico.pico_coreness_tasks([], pe, tune, None, 0) == pico.PICO_EINVAL
     # server configuration errors come before the device check
     cfg = pico.ServerConfig()
@@ -85,9 +85,9 @@ def test_task_and_server_argument_checks_need_no_device():
     cfg.max_inflight, cfg.arena, cfg.arena_bytes = 2, 4096 + 8, 1 << 20  # misaligned arena
     assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
     cfg.arena = 4096
-    cfg.giant_window = -1
+    cfg.max_large_slots = -1
     assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
-    cfg.giant_window = 0
+    cfg.max_large_slots = 0
     cfg.class_bounds[0], cfg.class_bounds[1] = 5000, 100  # bounds out of order
     assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
     assert ctypes.sizeof(pico.ServerConfig) == 4 + 4 + 8 + 8 + 8 + 16 + 16 + 4 + 4

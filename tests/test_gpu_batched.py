@@ -69,3 +69,42 @@ def test_batched_edge_cases():
     for algo in ("peelone", "histocore"):
         got = pico.coreness_batched(d, algo).cpu().numpy()
         assert np.array_equal(got, want), algo
+
+
+@pytest.mark.parametrize("lds_bytes", [0, -1])
+def test_batched_peelone_with_helpers(batch, lds_bytes):
+    """PeelOne graphs above a (here small) vertex count are decomposed by
+    their workgroup with idle workgroups claiming chunks of each phase; the
+    result is the oracle's either way."""
+    want = np.concatenate(_per_graph_oracle(batch))
+    d = batch.to("cuda")
+    tune = pico.BatchTune(lds_bytes, 0, 0, 1000)
+    got, st = pico.coreness_batched(d, "peelone", tune=tune, with_stats=True)
+    print(f"helpers lds_bytes={lds_bytes} stats={st}", flush=True)
+    assert np.array_equal(got.cpu().numpy(), want)
+    assert st["helped_graphs"] > 0
+
+
+def test_few_large_graphs_mostly_helped():
+    """Three large graphs in a launch of hundreds of workgroups: nearly all
+    of them help, and every phase's chunks are shared out."""
+    parts = [gg.rmat(15, 16, 41), gg.er_gnp(20_000, 10.0, 42), gg.scaled_rmat_block(14, 43, 200, 0.6, 44)]
+    srcs, dsts, sizes, base = [], [], [], 0
+    for p in parts:
+        s, t = p.edge_pairs()
+        srcs.append(s + base)
+        dsts.append(t + base)
+        sizes.append(p.n)
+        base += p.n
+    b = gg.pack_pairs(torch.tensor(sizes), torch.cat(srcs), torch.cat(dsts), name="three-large")
+    want = np.concatenate([oracle.bz_coreness(p.offsets, p.cols) for p in parts])
+    d = b.to("cuda")
+    for help_min in (1000, -1):
+        got, st = pico.coreness_batched(d, "peelone", tune=pico.BatchTune(0, 0, 0, help_min),
+                                        with_stats=True)
+        print(f"help_min={help_min} stats={st}", flush=True)
+        assert np.array_equal(got.cpu().numpy(), want), help_min
+        if help_min > 0:
+            assert st["helped_graphs"] == 3 and st["help_chunks"] > 0
+        else:
+            assert st["helped_graphs"] == 0

@@ -63,10 +63,9 @@ def test_tasks_match_oracle(pool, algo):
 def test_server_alone_vs_mix(pool, algo):
     """Requests arrive in bursts while earlier ones run; the arena admits only
     part of them at a time, up to three launches are in flight, and small
-    class bounds spread the pool over all three size classes (the largest go
-    through exclusive windows of the single-graph path with PeelOne, whose
-    rows here do not start at position 0).  Each result equals the graph's
-    result alone (the plain single-graph call) and the oracle's."""
+    class bounds spread the pool over all three size classes.  Each result
+    equals the graph's result alone (the plain single-graph call) and the
+    oracle's."""
     b, graphs = pool
     code = pico.ALGOS[algo]
     alone = []
@@ -80,11 +79,10 @@ def test_server_alone_vs_mix(pool, algo):
         alone.append(core.cpu().numpy())
     for g, a in zip(graphs, alone):
         assert np.array_equal(a, g["want"])
-    need = [max(pico.pico_task_scratch_bytes(g["n"], g["m"], code),
-                pico.pico_workspace_bytes(g["n"], g["m"], code | pico.PICO_OFFSETS_I64)) for g in graphs]
+    need = [pico.pico_task_scratch_bytes(g["n"], g["m"], code) for g in graphs]
     arena = max(3 * max(need), 1 << 20)  # well below the sum over all requests
     srv = pico.Server(algo, arena_bytes=arena, max_inflight=3, max_tasks_per_launch=16,
-                      class_bounds=(2000, 12000), giant_window=5)
+                      class_bounds=(2000, 12000), max_large_slots=1)
     rng = np.random.default_rng(5)
     R = 300
     pick = rng.integers(0, len(graphs), R)
