@@ -503,9 +503,10 @@ int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int algo,
     hipStream_t s = static_cast<hipStream_t>(stream);
     pico_task *dev = tasks_table(workspace, ws_bytes, num_tasks);
     PICO_HIP_TRY(hipMemcpyAsync(dev, tasks, sizeof(pico_task) * num_tasks, hipMemcpyHostToDevice, s));
-    int64_t max_n = 0;
-    for (int64_t i = 0; i < num_tasks; ++i) max_n = tasks[i].n > max_n ? tasks[i].n : max_n;
-    rc = run_tasks_device(dev, num_tasks, a, workspace, ws_bytes, tune, stats, s, max_n);
+    const int hm = help_min_large(tune, a);
+    int64_t n_large = 0;
+    for (int64_t i = 0; i < num_tasks; ++i) n_large += (hm > 0 && tasks[i].n >= hm) ? 1 : 0;
+    rc = run_tasks_device(dev, num_tasks, a, workspace, ws_bytes, tune, stats, s, n_large);
     if (rc) {
         g_prof.pending.clear();
         g_prof.used = 0;

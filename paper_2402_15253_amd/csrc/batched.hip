@@ -897,14 +897,15 @@ int help_min_of(const pico_batch_tune *tune) {
     return tune->help_min_vertices < 0 ? 0 : tune->help_min_vertices;
 }
 
-// big_task: some task may take helpers (then the grid is full even for few
-// tasks, so that idle workgroups exist to help).
+constexpr long long kHelpersPerBig = 32;  // extra workgroups per large task in a task-list launch
+
+// want: workgroups wanted (the task count, plus helpers for large tasks);
+// the grid is the smaller of that and what the device holds.
 int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune *tune,
-                 BatchState *st, pico_batch_stats *stats, hipStream_t stream, bool big_task) {
+                 BatchState *st, pico_batch_stats *stats, hipStream_t stream, long long want) {
     Launch L;
     const int help_min = algo == PICO_ALGO_PEELONE ? help_min_of(tune) : 0;
-    const bool full = help_min > 0 && big_task;
-    int rc = launch_config(reinterpret_cast<const void *>(batched_kernel), tune, full ? (1ll << 40) : T, &L);
+    int rc = launch_config(reinterpret_cast<const void *>(batched_kernel), tune, want, &L);
     if (rc) return rc;
     if (L.blocks > kMaxGrid) L.blocks = kMaxGrid;
     BatchArgs a;
@@ -961,6 +962,10 @@ size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo) {
     return b;
 }
 
+int help_min_large(const pico_batch_tune *tune, int algo) {
+    return (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? help_min_of(tune) : 0;
+}
+
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo) {
     long long words = 4 * task_al(n);
     if ((algo & PICO_ALGO_MASK) == PICO_ALGO_HISTOCORE) words += task_al(n) + task_al(m);
@@ -1006,12 +1011,13 @@ int run_batched(const long long *vptr, const long long *off, const int32_t *cols
     PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st);
     PICO_LAUNCH("packed_tasks", packed_tasks, dim3((unsigned)((G + 255) / 256)), dim3(256), stream, p,
                 tasks, st);
-    return launch_tasks(tasks, G, algo, tune, st, stats, stream, true);
+    // a packed batch fills the device: its tail is helped by whoever is idle
+    return launch_tasks(tasks, G, algo, tune, st, stats, stream, G > kMaxGrid ? G : kMaxGrid);
 }
 
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
                      const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream,
-                     int64_t max_n) {
+                     int64_t n_large) {
     Carve cv{static_cast<char *>(ws), 0, ws_bytes};
     Task *tasks = cv.take<Task>(T);
     cv.take<pico_task>(T);
@@ -1023,8 +1029,9 @@ int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, 
     PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st);
     PICO_LAUNCH("public_tasks", public_tasks, dim3((unsigned)((T + 255) / 256)), dim3(256), stream,
                 dev_tasks, (long long)T, algo == PICO_ALGO_HISTOCORE ? 1 : 0, tasks);
-    const int hm = help_min_of(tune);
-    return launch_tasks(tasks, T, algo, tune, st, stats, stream, hm > 0 && max_n >= hm);
+    // a few helpers per large task, so that a launch holding one large graph
+    // leaves room on the device for the launches beside it
+    return launch_tasks(tasks, T, algo, tune, st, stats, stream, T + kHelpersPerBig * n_large);
 }
 
 // Device copy of a host task array inside the tasks workspace (second slot).

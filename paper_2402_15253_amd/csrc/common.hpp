@@ -569,11 +569,13 @@ size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo);
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo);
 size_t tasks_ws_bytes(int64_t T);
 pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T);
-// max_n: the largest vertex count among the tasks (decides whether the grid
-// is filled for helpers).
+// n_large: how many tasks will take helpers (help_min_large); the grid gets a
+// few extra workgroups for each.
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
                      const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream,
-                     int64_t max_n);
+                     int64_t n_large);
+// vertex count from which a PeelOne task takes helpers (0 = never)
+int help_min_large(const pico_batch_tune *tune, int algo);
 int check_device();
 size_t ws_bytes_for(int64_t n, int64_t m, int algo);
 

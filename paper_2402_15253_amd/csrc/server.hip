@@ -220,8 +220,11 @@ int launch(pico_server *s, Slot &sl, int cls) {
     pico_task *dev = tasks_table(sl.ws, sl.ws_bytes, T);
     PICO_HIP_TRY(hipMemcpyAsync(dev, sl.staging, sizeof(pico_task) * T, hipMemcpyHostToDevice, sl.stream));
     const int algo = s->cfg.algo & PICO_ALGO_MASK;
+    const int hm = help_min_large(&s->cfg.tune, algo);
+    int64_t n_large = 0;
+    for (const Req &r : sl.reqs) n_large += (hm > 0 && r.r.n >= hm) ? 1 : 0;
     int rc = run_tasks_device(dev, T, algo, sl.ws, sl.ws_bytes, &s->cfg.tune, nullptr, sl.stream,
-                              sl.reqs.front().r.n);  // largest first
+                              n_large);
     if (rc) return rc;
     PICO_HIP_TRY(hipEventRecord(sl.done, sl.stream));
     sl.cls = cls;
