@@ -570,7 +570,12 @@ __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shar
     const long long nch = (items + chunk - 1) / chunk;
     const bool open = shared && nch > 1;
     if (threadIdx.x == 0) {
-        job->p = p;
+        st_rlx(&job->p.task, p.task);
+        st_rlx(&job->p.lo, p.lo);
+        st_rlx(&job->p.hi, p.hi);
+        st_rlx(&job->p.phase, p.phase);
+        st_rlx(&job->p.k, p.k);
+        st_rlx(&job->p.cur, p.cur);
         if (open) {
             st_rlx(&job->x.done, 0ull);
             // 16-bit sequence; 2^16 is even, so the parity survives the wrap
@@ -591,10 +596,12 @@ __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shar
         run_chunk(t, p, &job->n, c0, c1, X, c);
         ++own;
     }
+    // every wave's stores and atomics performed before the count below: the
+    // workgroup barrier does not wait for other waves' vector-memory traffic
+    fence_release();
     __syncthreads();
     if (threadIdx.x == 0) {
         if (open) {
-            fence_release();
             unsigned long long d = atomicAdd(&job->x.done, (unsigned long long)own) + own;
             const unsigned long long t0 = wall_clock64();
             while (d < (unsigned long long)nch) {  // chunks still being run by helpers
@@ -730,14 +737,25 @@ __device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
         if (jx == -2) break;
         if (ci < 0) continue;
         Job *job = &a.st->jobs[jx];
-        const JobParams p = job->p;
+        // The record is rewritten every phase: read it with atomic loads, never
+        // from a line this XCD's L2 may still hold from an earlier phase.
+        JobParams p;
+        p.task = ld_rlx(&job->p.task);
+        p.lo = ld_rlx(&job->p.lo);
+        p.hi = ld_rlx(&job->p.hi);
+        p.phase = ld_rlx(&job->p.phase);
+        p.k = ld_rlx(&job->p.k);
+        p.cur = ld_rlx(&job->p.cur);
+        p.pad = 0;
         const Task t = a.tasks[p.task];
         const long long chunk = p.phase == PH_DRAIN ? kChunkQueue : kChunkItems;
         const long long c0 = p.lo + ci * chunk, c1 = c0 + chunk < p.hi ? c0 + chunk : p.hi;
         run_chunk(t, p, &job->n, c0, c1, X, c);
+        // every wave's stores and atomics performed before the chunk is counted
+        // (the workgroup barrier does not wait for vector-memory traffic)
+        fence_release();
         __syncthreads();
         if (threadIdx.x == 0) {
-            fence_release();  // the chunk's writes before its count
             atomicAdd(&job->x.done, 1ull);
             atomicAdd(&a.st->helpchunks.v, 1ull);
         }

@@ -195,6 +195,9 @@ template <int NSNAP = kNumCtr, typename Rel = NoRelease>
 __device__ __forceinline__ bool grid_sync(GridState *gs, unsigned nblocks, unsigned long long limit,
                                           unsigned long long *snap_out, unsigned long long &bar_no,
                                           Rel on_release = Rel()) {
+    // every wave's stores and atomics are performed before the block arrives:
+    // the workgroup barrier waits for LDS traffic only
+    fence_release();
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned ngroups = nblocks < (unsigned)kBarGroups ? nblocks : (unsigned)kBarGroups;

@@ -136,3 +136,35 @@ def test_persistent_queue_server_alone_vs_mix():
     alone-versus-mix check as test_server_alone_vs_mix, with one kernel
     instance taking requests from a host ring."""
     raise AssertionError("persistent queue mode is switched off")
+
+
+def test_helped_tasks_repeatable():
+    """Large PeelOne tasks decomposed with 32 helpers each, next to small
+    ones, repeated: every run equals the single-graph result.  (Helpers count
+    a chunk done only after every wave of the workgroup has its stores and
+    atomics performed.)"""
+    b = gg.mixed_batch(6, 150_000, 300_000, seed=91, device="cuda")
+    code = pico.PICO_ALGO_PEELONE
+    alone, keep, tasks = [], [], []
+    for g in range(b.num_graphs):
+        x0, x1 = int(b.vptr[g]), int(b.vptr[g + 1])
+        off = b.offsets[x0:x1 + 1]
+        n, m = x1 - x0, int(off[-1] - off[0])
+        e0 = int(off[0])
+        alone.append(pico.coreness((off - e0).contiguous(), b.cols[e0:e0 + m], "peelone").cpu().numpy())
+        out = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        s = _scratch(n, m, code)
+        keep.append((out, s))
+        tasks.append(pico.Task(off.data_ptr(), b.cols.data_ptr(), n, m, out.data_ptr(), s.data_ptr(),
+                               s.numel()))
+    order = sorted(range(len(tasks)), key=lambda i: -tasks[i].n)
+    wsb = pico.pico_tasks_workspace_bytes(len(tasks))
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    for rep in range(4):
+        st = pico.BatchStats()
+        rc = pico.pico_coreness_tasks([tasks[i] for i in order], code, pico.BatchTune(-1, 0, 0, 32768),
+                                      ws, wsb, st)
+        assert rc == pico.PICO_OK, pico.pico_last_error()
+        assert st.helped_graphs == len(tasks) and st.help_chunks > 0
+        for i in range(len(tasks)):
+            assert np.array_equal(keep[i][0].cpu().numpy(), alone[i]), f"rep {rep} graph {i}"
