@@ -398,6 +398,37 @@ def plant_block(n: int, size: int, p: float, seed: int, *, device="cpu"):
     return members[ii], members[jj], members
 
 
+def edit_edges(g: CSRGraph, delete_frac: float, insert: int, seed: int) -> tuple:
+    """A changed copy of g for core maintenance: each undirected edge is
+    deleted with probability `delete_frac` (its 32-bit draw below
+    delete_frac * 2**32), then `insert` random vertex pairs are added (pairs
+    that are loops or already edges add nothing).  Returns (new graph, number
+    of undirected edges actually inserted), offsets of g's dtype."""
+    src, dst = g.edge_pairs()
+    upper = src < dst  # one entry per undirected edge
+    s, d = src[upper], dst[upper]
+    key = s * g.n + d
+    draw = uniform_u32(stream_seed(seed, 0xDE1), key)
+    keep = draw >= int(round(delete_frac * 2**32))
+    s, d = s[keep], d[keep]
+    ins = 0
+    if insert > 0 and g.n > 1:
+        idx = torch.arange(insert, device=src.device)
+        a = (uniform_u32(stream_seed(seed, 0x1A5), idx) % g.n).to(torch.int64)
+        b = (uniform_u32(stream_seed(seed, 0x1A6), idx) % g.n).to(torch.int64)
+        lo, hi = torch.minimum(a, b), torch.maximum(a, b)
+        new = torch.unique(lo * g.n + hi)
+        new = new[(new // g.n) != (new % g.n)]
+        old = torch.unique(s * g.n + d)
+        fresh = new[~torch.isin(new, old)]
+        ins = int(fresh.numel())
+        s = torch.cat([s, fresh // g.n])
+        d = torch.cat([d, fresh % g.n])
+    h = csr_from_pairs(g.n, s, d, offsets_dtype=g.offsets.dtype,
+                       name=f"{g.name}+edit(del={delete_frac},ins={insert},seed={seed})")
+    return h, ins
+
+
 def fingerprint(g: CSRGraph) -> str:
     """A 64-bit checksum of the CSR (n, m and every (row, col) entry)."""
     src, dst = g.edge_pairs()

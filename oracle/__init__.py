@@ -10,6 +10,9 @@ Routines (each cites the passage of the paper it follows):
   plain definition of coreness from Section I.  Related work, Section VI-A.
 * ``hindex_jacobi``  -- the Index2core paradigm (Section II-A, Alg. 2) in
   synchronous rounds, h-index by sorting (C).
+* ``hindex_jacobi_from`` -- the same iteration started from upper bounds of
+  the coreness (core maintenance after edge changes), never raising a value
+  (C).
 * ``brute_coreness`` -- the definition literally: for each k, delete vertices
   of degree < k until none is left; survivors form the k-core (pure Python,
   tiny graphs only).
@@ -70,6 +73,10 @@ def _load():
         lib.oracle_hindex_jacobi.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
+        lib.oracle_hindex_jacobi_from.restype = ctypes.c_int64
+        lib.oracle_hindex_jacobi_from.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -117,6 +124,27 @@ def hindex_jacobi(offsets, cols, max_rounds: int = 1 << 30):
                                      _ptr(x), _ptr(per_round), _ptr(last))
     if r < 0:
         raise RuntimeError(f"oracle_hindex_jacobi failed with {r}")
+    return x, per_round[:r].tolist(), last
+
+
+def hindex_jacobi_from(offsets, cols, x0, add: int = 0, max_rounds: int = 1 << 30):
+    """The synchronous h-index iteration started from upper bounds x0 (+ add)
+    of the coreness, capped by the degree, each round keeping the smaller of a
+    vertex's value and the h-index of its neighbours' values (core
+    maintenance on a changed graph).  Returns as ``hindex_jacobi``."""
+    off, adj = _csr_np(offsets, cols)
+    n = off.shape[0] - 1
+    start = np.ascontiguousarray(np.asarray(x0, dtype=np.int32))
+    if start.shape != (max(n, 0),):
+        raise ValueError("x0 must hold one value per vertex")
+    x = np.zeros(max(n, 0), dtype=np.int32)
+    cap = int(min(max_rounds, max(n, 1) + 1))
+    per_round = np.zeros(cap, dtype=np.int64)
+    last = np.zeros(max(n, 0), dtype=np.int32)
+    r = _load().oracle_hindex_jacobi_from(n, _ptr(off), _ptr(adj) if adj.size else None, _ptr(start),
+                                          int(add), cap, _ptr(x), _ptr(per_round), _ptr(last))
+    if r < 0:
+        raise RuntimeError(f"oracle_hindex_jacobi_from failed with {r}")
     return x, per_round[:r].tolist(), last
 
 

@@ -16,6 +16,9 @@
  *                          Section I: core(v) = the largest k such that v lies
  *                          in the k-core, the maximal subgraph of minimum
  *                          degree >= k.
+ *  - oracle_hindex_jacobi_from: the same iteration started from upper bounds
+ *                          of the coreness (core maintenance on a changed
+ *                          graph), never raising a value.
  *  - oracle_hindex_jacobi: the Index2core paradigm (Section II-A, Alg. 2) run
  *                          in synchronous rounds: x_0 = deg and
  *                          x_{t+1}(v) = H({x_t(u) : u in nbr(v)}), where H is
@@ -149,6 +152,65 @@ int64_t oracle_hindex_jacobi(int64_t n, const int64_t *off, const int32_t *adj,
             int64_t d = off[v + 1] - off[v];
             for (int64_t j = 0; j < d; ++j) buf[j] = x[adj[off[v] + j]];
             y[v] = h_index_sorted(buf, d);
+            if (y[v] != x[v]) {
+                ++changed;
+                if (changed_round_of) changed_round_of[v] = (int32_t)t;
+            }
+        }
+        if (changed == 0) break;
+        if (changed_per_round) changed_per_round[t - 1] = changed;
+        rounds = t;
+        int32_t *tmp = x; x = y; y = tmp;
+    }
+    memcpy(x_out, x, sizeof(int32_t) * (size_t)n);
+    free(x); free(y); free(buf);
+    return rounds;
+}
+
+/*
+ * The same synchronous iteration started from given upper bounds x0 of the
+ * coreness instead of the degrees (core maintenance: after edge deletions
+ * the old coreness is such a bound, after b insertions the old coreness
+ * plus b).  The start is x_0(v) = min(deg(v), max(x0[v] + add, 1)) on
+ * vertices with neighbours and 0 on isolated ones, and each round sets
+ * x_{t+1}(v) = min(x_t(v), H(x_t)(v)): a value never rises.  (From the
+ * degrees H never raises a value, so this is the iteration above.)  The
+ * iterates stay >= the coreness and stop at a vector with x <= H(x), which
+ * is at most the coreness, so they end at the coreness.
+ * Arguments and return value as oracle_hindex_jacobi; x0 may not be NULL.
+ */
+int64_t oracle_hindex_jacobi_from(int64_t n, const int64_t *off, const int32_t *adj,
+                                  const int32_t *x0, int64_t add, int64_t max_rounds,
+                                  int32_t *x_out, int64_t *changed_per_round,
+                                  int32_t *changed_round_of)
+{
+    if (n < 0 || (n > 0 && (!off || !x_out || !x0)) || max_rounds < 0) return -1;
+    if (n == 0) return 0;
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t d = off[v + 1] - off[v];
+        if (d > maxdeg) maxdeg = d;
+    }
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *y = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+    if (!x || !y || !buf) { free(x); free(y); free(buf); return -2; }
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t d = off[v + 1] - off[v];
+        int64_t b = (int64_t)x0[v] + add;
+        if (b < 1) b = 1;
+        x[v] = (int32_t)(d == 0 ? 0 : (b < d ? b : d));
+    }
+    if (changed_round_of) memset(changed_round_of, 0, sizeof(int32_t) * (size_t)n);
+
+    int64_t rounds = 0;
+    for (int64_t t = 1; t <= max_rounds; ++t) {
+        int64_t changed = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            int64_t d = off[v + 1] - off[v];
+            for (int64_t j = 0; j < d; ++j) buf[j] = x[adj[off[v] + j]];
+            int32_t h = h_index_sorted(buf, d);
+            y[v] = h < x[v] ? h : x[v];
             if (y[v] != x[v]) {
                 ++changed;
                 if (changed_round_of) changed_round_of[v] = (int32_t)t;

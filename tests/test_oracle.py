@@ -263,3 +263,90 @@ def test_planted_mistake_is_caught():
         return core
     caught = any(bad_peel(6, e) != oracle.brute_coreness(6, e) for e in _all_graphs(6))
     assert caught
+
+
+# ---------------------------------------------------------------- core maintenance
+# The iteration from upper bounds (hindex_jacobi_from) is pinned to the plain
+# iteration from the degrees, to BZ and brute force on the changed graph, and
+# to the facts that make it a maintenance method: deleting edges never raises
+# a coreness, one insertion raises any coreness by at most one, and a start
+# below the coreness is not repaired (values never rise).
+
+MAINT_GRAPHS = [lambda: gg.rmat(10, 8, 3), lambda: gg.er_gnp(600, 6.0, 4), lambda: gg.g1(),
+                lambda: gg.disjoint_union(gg.complete(12), gg.cycle(9), gg.star(20), gg.empty_graph(3))]
+
+
+@pytest.mark.parametrize("gi", range(len(MAINT_GRAPHS)))
+def test_jacobi_from_degrees_is_the_plain_iteration(gi):
+    g = MAINT_GRAPHS[gi]()
+    x, pr, last = oracle.hindex_jacobi(g.offsets, g.cols)
+    deg = g.degrees().numpy().astype(np.int32)
+    y, pr2, last2 = oracle.hindex_jacobi_from(g.offsets, g.cols, deg)
+    assert np.array_equal(x, y) and pr == pr2 and np.array_equal(last, last2)
+    # any start at or above the degree is capped to it
+    z, pr3, _ = oracle.hindex_jacobi_from(g.offsets, g.cols, deg, add=1000)
+    assert np.array_equal(x, z) and pr == pr3
+
+
+@pytest.mark.parametrize("gi", range(len(MAINT_GRAPHS)))
+@pytest.mark.parametrize("add", [0, 1, 7])
+def test_jacobi_from_upper_bounds_reaches_coreness(gi, add):
+    g = MAINT_GRAPHS[gi]()
+    core = oracle.bz_coreness(g.offsets, g.cols)
+    x, pr, _ = oracle.hindex_jacobi_from(g.offsets, g.cols, core, add=add)
+    assert np.array_equal(x, core)
+    if add == 0:
+        assert pr == []  # the coreness is a fixed point: nothing changes
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_maintenance_after_deletions_and_insertions(seed):
+    g = gg.rmat(11, 8, 40 + seed) if seed % 2 else gg.er_gnp(1500, 8.0, 40 + seed)
+    old = oracle.bz_coreness(g.offsets, g.cols)
+    # deletions only: the old coreness bounds the new one
+    h, ins = gg.edit_edges(g, 0.03, 0, seed)
+    assert ins == 0 and h.m < g.m
+    new = oracle.bz_coreness(h.offsets, h.cols)
+    assert (new <= old).all()
+    x, pr, _ = oracle.hindex_jacobi_from(h.offsets, h.cols, old)
+    assert np.array_equal(x, new)
+    cold = oracle.hindex_jacobi(h.offsets, h.cols)[1]
+    assert len(pr) <= len(cold) and sum(pr) <= sum(cold)
+    # deletions and b insertions: old + b bounds the new coreness
+    h2, b = gg.edit_edges(g, 0.01, 25, seed)
+    assert b > 0
+    new2 = oracle.bz_coreness(h2.offsets, h2.cols)
+    assert (new2 <= old + b).all()
+    x2, _, _ = oracle.hindex_jacobi_from(h2.offsets, h2.cols, old, add=b)
+    assert np.array_equal(x2, new2)
+
+
+def test_one_insertion_raises_coreness_by_at_most_one():
+    g = gg.er_gnp(300, 5.0, 9)
+    core = oracle.bz_coreness(g.offsets, g.cols)
+    for trial in range(20):
+        h, ins = gg.edit_edges(g, 0.0, 1, 100 + trial)
+        new = oracle.bz_coreness(h.offsets, h.cols)
+        assert ((new - core) >= 0).all() and ((new - core) <= 1).all()
+        x, _, _ = oracle.hindex_jacobi_from(h.offsets, h.cols, core, add=ins)
+        assert np.array_equal(x, new)
+
+
+@pytest.mark.parametrize("n", [5, 6, 7])
+def test_maintenance_brute_force_tiny(n):
+    rng = random.Random(n)
+    pairs = list(itertools.combinations(range(n), 2))
+    for _ in range(25):
+        edges = [p for p in pairs if rng.random() < 0.5]
+        g = gg.from_edge_list(n, edges)
+        want = oracle.brute_coreness(n, edges)
+        # random upper bounds: coreness plus a random non-negative slack
+        start = np.array([c + rng.randrange(0, 4) for c in want], dtype=np.int32)
+        x, _, _ = oracle.hindex_jacobi_from(g.offsets, g.cols, start)
+        assert x.tolist() == want
+
+
+def test_start_below_coreness_is_not_repaired():
+    g = gg.complete(8)  # coreness 7 everywhere
+    x, pr, _ = oracle.hindex_jacobi_from(g.offsets, g.cols, np.full(8, 3, dtype=np.int32))
+    assert (x == 3).all() and pr == []
