@@ -67,7 +67,8 @@ def algorithmic_bytes(algo: str, st: dict, n: int, m: int, w: int) -> float:
     return init + rounds + 4 * n
 
 
-KERNELS = {"peelone": "po_persistent", "histocore": "hc_persistent"}
+# decomposition kernels by algorithm: grid-wide persistent, one workgroup
+KERNELS = {"peelone": ("po_persistent", "po_small"), "histocore": ("hc_persistent", "hc_small")}
 
 
 def coreness_properties(offsets, cols, x) -> dict:
@@ -346,7 +347,7 @@ def bench_serving(args, pico, torch, np):
     medges = ep[1:] - ep[:-1]
     req_n = sizes[pick.numpy()]
     base = np.concatenate([[0], np.cumsum(req_n)])
-    out = torch.empty(int(base[-1]) + 1, dtype=torch.int32, device=dev)
+    out = torch.full((int(base[-1]) + 1,), -1, dtype=torch.int32, device=dev)  # -1: never written
     off_ptr = [pool.offsets.data_ptr() + 8 * int(vp[g]) for g in range(pool.num_graphs)]
     cols_ptr = pool.cols.data_ptr()
     out_ptr = out.data_ptr()
@@ -396,9 +397,14 @@ def bench_serving(args, pico, torch, np):
     same = True
     for r in range(R):
         g = int(pk[r])
-        if not torch.equal(out[base[r]:base[r + 1]], ref[vp[g]:vp[g + 1]]):
+        got, want = out[base[r]:base[r + 1]], ref[vp[g]:vp[g + 1]]
+        if not torch.equal(got, want):
             same = False
-            log(f"request {r} (graph {g}) differs from the graph alone")
+            bad = torch.nonzero(got != want).flatten()
+            ex = [(int(v), int(got[v]), int(want[v])) for v in bad[:6].tolist()]
+            log(f"request {r} (graph {g}, n={int(sizes[g])}, arrival {arr[r]:.3f}s) differs from the "
+                f"graph alone at {bad.numel()} vertices ({int((got[bad] == -1).sum())} never written); "
+                f"(vertex, served, alone): {ex}")
             break
     # the serial plain loop on the same trace (capped in wall time)
     ws_stream = torch.cuda.current_stream()
@@ -452,13 +458,104 @@ def bench_serving(args, pico, torch, np):
         sys.exit(1)
 
 
+def bench_update(args, pico, torch, np):
+    """Core maintenance on RMAT-22: the coreness after deleting 0.1% of the
+    undirected edges (and, second, after inserting 16 edges), by HistoCore
+    started from the old coreness (pico_coreness_update), against cold
+    HistoCore and PeelOne on the changed graph."""
+    import graphgen as gg
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    g = gg.rmat22(device=dev)
+    old = pico.coreness(g.offsets, g.cols, "peelone")
+    cases = {}
+    for name, frac, ins in (("delete 0.1%", 0.001, 0), ("insert 16", 0.0, 16)):
+        h, b = gg.edit_edges(g, frac, ins, 2201)
+        cases[name] = (h, b)
+    torch.cuda.synchronize()
+    log(f"RMAT-22 n={g.n} m={g.m}; edits generated in {time.perf_counter() - t0:.1f}s")
+    code_hc = pico.algo_code("histocore", g.offsets)
+    ws_bytes = max(pico.pico_workspace_bytes(h.n, h.m, code_hc) for h, _ in cases.values())
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    w = 8 if g.offsets.dtype == torch.int64 else 4
+    per, first = {}, None
+    for name, (h, b) in cases.items():
+        out = torch.empty(h.n, dtype=torch.int32, device=dev)
+        st = pico.PicoStats()
+
+        def update():
+            rc = pico.pico_coreness_update(h.offsets, h.cols, h.n, h.m, code_hc, old, b, out, ws, ws_bytes,
+                                           st, None)
+            if rc != pico.PICO_OK:
+                raise pico.PicoError(rc, pico.pico_last_error())
+
+        for _ in range(args.warmup):
+            update()
+        torch.cuda.synchronize()
+        pico.pico_profile_enable(not args.no_profile)
+        tw = time.perf_counter()
+        for _ in range(args.steps):
+            update()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - tw) / args.steps
+        prof = pico.pico_profile_read() if not args.no_profile else {}
+        pico.pico_profile_enable(False)
+        sd = st.as_dict()
+        cold_hc, st_hc = pico.coreness(h.offsets, h.cols, "histocore", workspace=ws, with_stats=True)
+        cold_po, st_po = pico.coreness(h.offsets, h.cols, "peelone", with_stats=True)
+        ok = bool(torch.equal(out, cold_po)) and bool(torch.equal(cold_hc, cold_po))
+        props = coreness_properties(h.offsets, h.cols, out)
+        ok = ok and all(props.values())
+        rec = {"inserted": b, "m": h.m, "update_ms": round(el * 1e3, 3),
+               "update_rounds": sd["iterations"], "update_frontier_total": sd["frontier_total"],
+               "cold_histocore_ms": round(st_hc["elapsed_ms"], 3), "cold_histocore_rounds": st_hc["iterations"],
+               "cold_histocore_frontier_total": st_hc["frontier_total"],
+               "cold_peelone_ms": round(st_po["elapsed_ms"], 3), "identical_to_cold": ok}
+        if "hc_persistent" in prof:
+            launches, t_ms = prof["hc_persistent"]
+            avg = t_ms / launches
+            rec["roofline"] = _roofline("hc_persistent", algorithmic_bytes("histocore", sd, h.n, h.m, w), avg,
+                                        "rmat22-update")
+        per[name] = rec
+        log(f"{name}: {rec}")
+        if first is None:
+            first = (name, h, rec)
+    name, h, rec = first
+    cpu = None
+    if args.cpu_budget > 0:
+        want, runs, t_cpu = cpu_baseline(h, args.cpu_budget)
+        cpu = {"value": round(h.m * runs / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"Batagelj-Zaversnik peel from scratch on the changed RMAT-22 ({name}), single "
+                         f"thread, {runs} run(s), {t_cpu:.1f}s"}
+        got = pico.coreness(h.offsets, h.cols, "peelone").cpu().numpy()
+        per[name]["identical_to_oracle"] = bool(np.array_equal(got, want))
+    ok = all(r["identical_to_cold"] and r.get("identical_to_oracle", True) for r in per.values())
+    out = {
+        "metric": "core maintenance GTEPS (|E| of the changed graph / update time)",
+        "value": round(h.m / (rec["update_ms"] / 1e3) / 1e9, 4), "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["update_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "RMAT-22 (scale 22, edge factor 16, seed 22, int32 CSR); each undirected "
+                               "edge deleted with probability 0.001 (seed 2201); HistoCore from the old "
+                               "coreness; second case: 16 random insertions, bound old + 16",
+                   "parallelism": "single GPU"},
+        "roofline": rec.get("roofline"), "cpu_baseline": cpu, "cases": per,
+        "parity": "identical to cold PeelOne and HistoCore" + (" and the oracle" if cpu else "")
+                  if ok else "MISMATCH",
+    }
+    print(json.dumps(out), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="rmat22",
-                    choices=["er10k", "rmat22", "rmat26", "batched", "serving"])
+                    choices=["er10k", "rmat22", "rmat26", "batched", "serving", "rmat22-update"])
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--algos", default="peelone,histocore",
@@ -499,6 +596,8 @@ def main():
         return bench_batched(args, pico, torch, np)
     if args.config == "serving":
         return bench_serving(args, pico, torch, np)
+    if args.config == "rmat22-update":
+        return bench_update(args, pico, torch, np)
     t0 = time.perf_counter()
     g, desc = make_graph(args.config, dev)
     torch.cuda.synchronize()
@@ -546,14 +645,15 @@ def main():
     # Roofline of the kernel that takes the most time: one persistent launch
     # per decomposition, timed with HIP events on the call's stream.
     roofline, per_kernel = None, {}
-    for algo, kname in KERNELS.items():
-        if kname not in prof:
-            continue
-        launches, t_ms = prof[kname]
-        b = algorithmic_bytes(algo, st[algo], n, m, w)
-        avg_s = t_ms / launches / 1e3
-        per_kernel[kname] = {"launches": launches, "avg_ms": round(t_ms / launches, 4),
-                             "alg_bytes": int(b), "alg_GBps": round(b / avg_s / 1e9, 1)}
+    for algo, knames in KERNELS.items():
+        for kname in knames:
+            if kname not in prof or algo not in st:
+                continue
+            launches, t_ms = prof[kname]
+            b = algorithmic_bytes(algo, st[algo], n, m, w)
+            avg_s = t_ms / launches / 1e3
+            per_kernel[kname] = {"launches": launches, "avg_ms": round(t_ms / launches, 4),
+                                 "alg_bytes": int(b), "alg_GBps": round(b / avg_s / 1e9, 1)}
     if per_kernel:
         kname = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"] * per_kernel[k]["launches"])
         pk = per_kernel[kname]

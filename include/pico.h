@@ -62,7 +62,17 @@ enum {
     PICO_ALGO_PEELONE = 0,
     PICO_ALGO_HISTOCORE = 1,
     PICO_ALGO_MASK = 0xff,
-    PICO_OFFSETS_I64 = 0x100 /* OR-ed into algo: csr_offsets is int64[n+1] */
+    PICO_OFFSETS_I64 = 0x100, /* OR-ed into algo: csr_offsets is int64[n+1] */
+    /* Path selection, OR-ed into algo (single-graph calls only; at most one).
+     * Without either flag a graph whose vertex values fit in one workgroup's
+     * LDS (n * 4 bytes, about 160 KiB on gfx950) and whose m is at most
+     * 2^14 (environment PICO_SMALL_MAX_EDGES overrides; 0 = never) is
+     * decomposed by one workgroup, the rest by the grid-wide persistent
+     * kernels.  Both paths compute the same coreness and statistics (the
+     * per-phase times in phase_ms are grid-path only). */
+    PICO_PATH_GRID = 0x200,   /* always the grid-wide persistent kernels */
+    PICO_PATH_WG = 0x400      /* always one workgroup; PICO_ENOTSUP if the
+                                 values do not fit in its LDS */
 };
 
 /* Run statistics (all counts over the whole call). */
@@ -129,6 +139,35 @@ PICO_API int pico_workspace_bytes(int64_t n, int64_t m, int algo, size_t *bytes)
 PICO_API int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
                      int algo, int32_t *out_core, void *workspace, size_t ws_bytes,
                      pico_stats *stats, void *stream);
+
+/*
+ * pico_coreness_update -- coreness of a graph that changed since a coreness
+ * was last computed (core maintenance, the dynamic-graph use of the h-index
+ * formulation that Section IV builds on): HistoCore (Alg. 6) started from
+ * upper bounds instead of the degrees.  The h-index iteration converges to
+ * the coreness from any vector of upper bounds, and a started run only
+ * lowers what is too high, so a small change costs few rounds.
+ *
+ *   prev_core  device int32[n]: for each vertex of the new graph a value such
+ *              that prev_core[v] + bound_add >= its new coreness.  Deleting
+ *              edges never raises a coreness, so after deletions the old
+ *              coreness with bound_add = 0 qualifies; inserting one edge raises
+ *              any coreness by at most one, so after b insertions (and any
+ *              deletions) the old coreness with bound_add = b does.  Vertices
+ *              new to the graph take any value >= their degree.  Values are
+ *              capped by the degree and raised to 1 on vertices with
+ *              neighbours.  With a bound below the coreness the result is
+ *              undefined.  May alias out_core (in-place update).
+ *   bound_add  >= 0, added to every prev_core value.
+ *   algo       PICO_ALGO_HISTOCORE (PeelOne cannot start from bounds:
+ *              PICO_ENOTSUP), optionally | PICO_OFFSETS_I64 and a path flag.
+ * Other arguments, workspace (pico_workspace_bytes for HistoCore) and errors
+ * as pico_coreness_ws.
+ */
+PICO_API int pico_coreness_update(const void *csr_offsets, const int32_t *csr_cols, int64_t n,
+                                  int64_t m, int algo, const int32_t *prev_core, int32_t bound_add,
+                                  int32_t *out_core, void *workspace, size_t ws_bytes,
+                                  pico_stats *stats, void *stream);
 
 /* Tuning of the batched kernel (NULL = defaults). */
 typedef struct pico_batch_tune {

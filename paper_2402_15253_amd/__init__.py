@@ -19,8 +19,10 @@ import torch  # loaded first so the library binds to the HIP runtime torch uses
 
 __all__ = [
     "PICO_OK", "PICO_EINVAL", "PICO_ENOMEM", "PICO_EHIP", "PICO_ENOTSUP", "PICO_EBADCSR",
-    "PICO_ALGO_PEELONE", "PICO_ALGO_HISTOCORE", "PICO_OFFSETS_I64", "PicoError", "PicoStats",
-    "pico_coreness", "pico_coreness_ws", "pico_workspace_bytes", "pico_validate_csr",
+    "PICO_ALGO_PEELONE", "PICO_ALGO_HISTOCORE", "PICO_OFFSETS_I64", "PICO_PATH_GRID", "PICO_PATH_WG",
+    "PATHS", "PicoError", "PicoStats",
+    "pico_coreness", "pico_coreness_ws", "pico_coreness_update", "coreness_update",
+    "pico_workspace_bytes", "pico_validate_csr",
     "pico_status_string", "pico_last_error", "pico_version", "coreness", "library_path",
     "load_library", "EXPORTED_SYMBOLS", "pico_profile_enable", "pico_profile_read",
     "pico_batched_workspace_bytes", "pico_coreness_batched", "coreness_batched", "BatchTune",
@@ -32,9 +34,11 @@ __all__ = [
 
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
 PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE, PICO_OFFSETS_I64 = 0, 1, 0x100
+PICO_PATH_GRID, PICO_PATH_WG = 0x200, 0x400
+PATHS = {None: 0, "auto": 0, "grid": PICO_PATH_GRID, "wg": PICO_PATH_WG}
 ALGOS = {"peelone": PICO_ALGO_PEELONE, "histocore": PICO_ALGO_HISTOCORE}
 
-EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_workspace_bytes",
+EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update", "pico_workspace_bytes",
                     "pico_validate_csr", "pico_status_string", "pico_last_error", "pico_version",
                     "pico_profile_enable", "pico_profile_read", "pico_batched_workspace_bytes",
                     "pico_coreness_batched", "pico_task_scratch_bytes",
@@ -155,6 +159,9 @@ def load_library():
     lib.pico_coreness_ws.argtypes = [vp, vp, i64, i64, i32, vp, vp, ctypes.c_size_t,
                                      ctypes.POINTER(PicoStats), vp]
     lib.pico_coreness_ws.restype = i32
+    lib.pico_coreness_update.argtypes = [vp, vp, i64, i64, i32, vp, ctypes.c_int32, vp, vp,
+                                         ctypes.c_size_t, ctypes.POINTER(PicoStats), vp]
+    lib.pico_coreness_update.restype = i32
     lib.pico_workspace_bytes.argtypes = [i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pico_workspace_bytes.restype = i32
     lib.pico_validate_csr.argtypes = [vp, vp, i64, i64, i32, vp]
@@ -350,8 +357,11 @@ def pico_validate_csr(csr_offsets, csr_cols, n: int, m: int, algo: int, stream=N
                                             _stream(stream))
 
 
-def algo_code(algo, offsets: torch.Tensor) -> int:
+def algo_code(algo, offsets: torch.Tensor, path=None) -> int:
+    """The C algo word: algorithm, offset width and path ("grid", "wg" or
+    None/"auto" for the library's choice by size)."""
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    a |= PATHS[path]
     if offsets.dtype == torch.int64:
         a |= PICO_OFFSETS_I64
     elif offsets.dtype != torch.int32:
@@ -366,17 +376,19 @@ def workspace_for(n: int, m: int, algo: int, device) -> torch.Tensor:
 
 
 def coreness(offsets: torch.Tensor, cols: torch.Tensor, algo="peelone", *, out=None,
-             workspace=None, with_stats: bool = False, stream=None):
+             workspace=None, with_stats: bool = False, stream=None, path=None):
     """Coreness of every vertex of a device-resident CSR graph (int32 tensor).
 
     ``offsets``: int32/int64 [n+1] on the GPU; ``cols``: int32 [m] on the GPU.
-    Raises PicoError on failure.  With ``with_stats`` returns (core, stats).
+    ``path``: None (by size), "grid" (persistent kernels) or "wg" (one
+    workgroup, values in LDS).  Raises PicoError on failure.  With
+    ``with_stats`` returns (core, stats).
     """
     if cols.dtype != torch.int32:
         raise TypeError("cols must be int32")
     n = offsets.numel() - 1
     m = cols.numel()
-    a = algo_code(algo, offsets)
+    a = algo_code(algo, offsets, path)
     if out is None:
         out = torch.empty(max(n, 0), dtype=torch.int32, device=offsets.device)
     if workspace is None:
@@ -384,6 +396,41 @@ def coreness(offsets: torch.Tensor, cols: torch.Tensor, algo="peelone", *, out=N
     st = PicoStats()
     _check(pico_coreness_ws(offsets, cols, n, m, a, out, workspace, workspace.numel(), st,
                             stream=stream))
+    return (out, st.as_dict()) if with_stats else out
+
+
+def pico_coreness_update(csr_offsets, csr_cols, n: int, m: int, algo: int, prev_core, bound_add: int,
+                         out_core, workspace, ws_bytes: int, stats: PicoStats | None = None,
+                         stream=None) -> int:
+    """C ``pico_coreness_update``; returns the status code."""
+    return load_library().pico_coreness_update(_ptr(csr_offsets), _ptr(csr_cols), n, m, algo,
+                                               _ptr(prev_core), bound_add, _ptr(out_core),
+                                               _ptr(workspace), ws_bytes,
+                                               ctypes.byref(stats) if stats is not None else None,
+                                               _stream(stream))
+
+
+def coreness_update(offsets: torch.Tensor, cols: torch.Tensor, prev_core: torch.Tensor,
+                    bound_add: int = 0, *, out=None, workspace=None, with_stats: bool = False,
+                    stream=None, path=None):
+    """Coreness of a changed graph from upper bounds ``prev_core + bound_add``
+    (HistoCore started from them): after edge deletions the old coreness with
+    bound_add 0, after b insertions the old coreness with bound_add b.
+    ``out`` may be ``prev_core`` (in-place update)."""
+    if cols.dtype != torch.int32 or prev_core.dtype != torch.int32:
+        raise TypeError("cols and prev_core must be int32")
+    n = offsets.numel() - 1
+    m = cols.numel()
+    if prev_core.numel() != max(n, 0):
+        raise ValueError("prev_core must hold one value per vertex")
+    a = algo_code("histocore", offsets, path)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=offsets.device)
+    if workspace is None:
+        workspace = workspace_for(n, m, a, offsets.device)
+    st = PicoStats()
+    _check(pico_coreness_update(offsets, cols, n, m, a, prev_core, bound_add, out, workspace,
+                                workspace.numel(), st, stream=stream))
     return (out, st.as_dict()) if with_stats else out
 
 

@@ -44,7 +44,7 @@ void *host_scratch(size_t bytes) {
     return buf;
 }
 
-int persistent_grid(const void *kernel, int block, int max_per_cu, int *blocks) {
+int persistent_grid(const void *kernel, int block, int max_per_cu, long long want, int *blocks) {
     int dev = 0;
     PICO_HIP_TRY(hipGetDevice(&dev));
     int cus = 0, coop = 0;
@@ -61,7 +61,11 @@ int persistent_grid(const void *kernel, int block, int max_per_cu, int *blocks) 
         set_error("persistent kernel does not fit on a compute unit");
         return PICO_ENOTSUP;
     }
-    *blocks = per_cu * cus;
+    long long b = (long long)per_cu * cus;
+    const int forced = tune_int("PICO_GRID_BLOCKS", 0);  // development override
+    if (forced > 0) want = forced;
+    if (want > 0 && want < b) b = want;
+    *blocks = (int)b;
     return PICO_OK;
 }
 
@@ -140,8 +144,12 @@ int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int a
         set_error("unknown algo %d", algo);
         return PICO_EINVAL;
     }
-    if ((algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64)) != 0) {
+    if ((algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64 | PICO_PATH_GRID | PICO_PATH_WG)) != 0) {
         set_error("unknown flag bits in algo 0x%x", algo);
+        return PICO_EINVAL;
+    }
+    if ((algo & PICO_PATH_GRID) && (algo & PICO_PATH_WG)) {
+        set_error("PICO_PATH_GRID and PICO_PATH_WG are exclusive");
         return PICO_EINVAL;
     }
     if (n < 0 || m < 0) {
@@ -168,9 +176,20 @@ int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int a
 }
 
 
+// warm / warm_add: HistoCore started from given upper bounds (nullptr: from
+// the degrees).
 int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo, int32_t *out,
-             void *ws, size_t ws_bytes, pico_stats *st, hipStream_t s) {
+             void *ws, size_t ws_bytes, pico_stats *st, hipStream_t s, const int32_t *warm = nullptr,
+             int warm_add = 0) {
     const bool i64 = (algo & PICO_OFFSETS_I64) != 0;
+    bool small = false;
+    int rc = small_path(n, m, algo, &small);
+    if (rc) return rc;
+    if (small)
+        return i64 ? run_small<int64_t>(static_cast<const int64_t *>(off), cols, n, m, algo, out, ws,
+                                        ws_bytes, st, s, warm, warm_add)
+                   : run_small<int32_t>(static_cast<const int32_t *>(off), cols, n, m, algo, out, ws,
+                                        ws_bytes, st, s, warm, warm_add);
     if ((algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE) {
         return i64 ? run_peelone<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
                                           ws_bytes, st, s)
@@ -178,9 +197,9 @@ int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int alg
                                           ws_bytes, st, s);
     }
     return i64 ? run_histocore<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
-                                        ws_bytes, st, s)
+                                        ws_bytes, st, s, warm, warm_add)
                : run_histocore<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws,
-                                        ws_bytes, st, s);
+                                        ws_bytes, st, s, warm, warm_add);
 }
 
 template <typename Off>
@@ -206,8 +225,11 @@ __global__ void validate_kernel(const Off *__restrict__ off, const int32_t *__re
 }  // namespace
 
 size_t ws_bytes_for(int64_t n, int64_t m, int algo) {
-    return (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m)
-                                                         : histocore_ws_bytes(n, m);
+    // enough for either path, so the path may change without a new workspace
+    const size_t grid = (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m)
+                                                                      : histocore_ws_bytes(n, m);
+    const size_t small = small_ws_bytes(n, m, algo);
+    return grid > small ? grid : small;
 }
 
 int check_device() {
@@ -299,10 +321,15 @@ int pico_workspace_bytes(int64_t n, int64_t m, int algo, size_t *bytes) {
     return PICO_OK;
 }
 
-int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
-                     int algo, int32_t *out_core, void *workspace, size_t ws_bytes,
-                     pico_stats *stats, void *stream) {
-    clear_error();
+}  // extern "C"
+
+namespace {
+
+// pico_coreness_ws and pico_coreness_update: warm == nullptr starts from the
+// degrees.
+int coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,
+                int32_t *out_core, void *workspace, size_t ws_bytes, pico_stats *stats, void *stream,
+                const int32_t *warm, int warm_add) {
     if (stats) memset(stats, 0, sizeof(*stats));
     int rc = check_args(csr_offsets, csr_cols, n, m, algo, out_core);
     if (rc) return rc;
@@ -320,7 +347,7 @@ int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n
     }
     auto t0 = std::chrono::steady_clock::now();
     rc = dispatch(csr_offsets, csr_cols, n, m, algo, out_core, workspace, ws_bytes, stats,
-                  static_cast<hipStream_t>(stream));
+                  static_cast<hipStream_t>(stream), warm, warm_add);
     if (rc) {
         g_prof.pending.clear();
         g_prof.used = 0;
@@ -334,6 +361,39 @@ int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return PICO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
+                     int algo, int32_t *out_core, void *workspace, size_t ws_bytes,
+                     pico_stats *stats, void *stream) {
+    clear_error();
+    return coreness_ws(csr_offsets, csr_cols, n, m, algo, out_core, workspace, ws_bytes, stats, stream,
+                       nullptr, 0);
+}
+
+int pico_coreness_update(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
+                         int algo, const int32_t *prev_core, int32_t bound_add, int32_t *out_core,
+                         void *workspace, size_t ws_bytes, pico_stats *stats, void *stream) {
+    clear_error();
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if ((algo & PICO_ALGO_MASK) != PICO_ALGO_HISTOCORE) {
+        set_error("pico_coreness_update runs HistoCore only (PeelOne cannot start from bounds)");
+        return (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? PICO_ENOTSUP : PICO_EINVAL;
+    }
+    if (bound_add < 0) {
+        set_error("bound_add must be >= 0 (got %d)", bound_add);
+        return PICO_EINVAL;
+    }
+    if (n > 0 && !prev_core) {
+        set_error("NULL prev_core with n=%lld", (long long)n);
+        return PICO_EINVAL;
+    }
+    return coreness_ws(csr_offsets, csr_cols, n, m, algo, out_core, workspace, ws_bytes, stats, stream,
+                       prev_core, bound_add);
 }
 
 int pico_coreness(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,

@@ -24,6 +24,8 @@
 // value.
 #include <climits>
 #include <cstddef>
+#include <cstdlib>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -32,6 +34,7 @@ namespace {
 
 constexpr int kBatchRounds = 4;  // edges per thread per expansion step
 constexpr int kSumWaveMinDefault = 64;
+constexpr long long kSmallMaxEdgesDefault = 1ll << 14;  // one-workgroup path, single graphs
 
 // ------------------------------------------------------------ helping
 //
@@ -95,14 +98,17 @@ struct BatchState {
 
 // One graph of a batch, as the kernel sees it.  `off` holds positions into
 // `cols` (not necessarily starting at 0); `histo` is indexed by position - e0.
-struct Task {
-    const long long *off;
+// Batches use 64-bit offsets; a single small graph may come with 32-bit ones.
+template <typename Off>
+struct TaskT {
+    const Off *off;
     const int32_t *cols;
     long long e0;
     int32_t *out, *core, *L0, *L1, *L2, *oldcore, *histo;
     int n;
     int pad;
 };
+using Task = TaskT<long long>;
 
 struct BatchArgs {
     const Task *tasks;
@@ -122,6 +128,7 @@ __host__ __device__ inline long long task_al(long long count) { return (count + 
 // Per-thread event counts, summed once per workgroup at exit.
 struct Counts {
     long long levels = 0, atomics = 0, lds = 0, frontier = 0, edges = 0, buckets = 0, pushes = 0;
+    long long scans = 0, drains = 0, kmax = 0;  // PeelOne schedule (uniform in the workgroup)
 };
 
 extern __shared__ int dyn_lds[];
@@ -164,10 +171,10 @@ __device__ __forceinline__ void wg_append(bool pred, int item, int32_t *list, un
 
 // ---------------------------------------------------------------- PeelOne
 
-template <bool kLds>
-__device__ void peel_graph(const Task &t, WgCounters &w, ExpandLds &X, Counts &c) {
+template <bool kLds, typename Off>
+__device__ void peel_graph(const TaskT<Off> &t, WgCounters &w, ExpandLds &X, Counts &c) {
     const int nv = t.n;
-    const long long *off = t.off;
+    const Off *off = t.off;
     Vals<kLds> cv{t.core};
     int32_t *out = t.out;
     int32_t *A[2] = {t.L0, t.L1};
@@ -199,6 +206,7 @@ __device__ void peel_graph(const Task &t, WgCounters &w, ExpandLds &X, Counts &c
     while (qtail < peelable) {
         // level scan: survivors at value k open the level's queue, the rest
         // (value > k) survive to the next scan
+        ++c.scans;
         if (threadIdx.x == 0) {
             w.b = 0;
             w.c = (unsigned)qtail;
@@ -233,6 +241,7 @@ __device__ void peel_graph(const Task &t, WgCounters &w, ExpandLds &X, Counts &c
         // w.c above before any append below moves it
         int lo = lo0, hi = hi0;
         while (lo < hi) {
+            ++c.drains;
             for (int base = lo; base < hi; base += kBlock) {
                 const int i = base + (int)threadIdx.x;
                 const int v = i < hi ? Q[i] : -1;
@@ -276,6 +285,7 @@ __device__ void peel_graph(const Task &t, WgCounters &w, ExpandLds &X, Counts &c
         }
         qtail = hi;
         ++c.levels;
+        c.kmax = k;
         k += 1;
     }
     c.frontier += peelable;
@@ -284,11 +294,13 @@ __device__ void peel_graph(const Task &t, WgCounters &w, ExpandLds &X, Counts &c
 
 // ---------------------------------------------------------------- HistoCore
 
-template <bool kLds>
-__device__ void histo_graph(const Task &t, int sum_wave_min, WgCounters &w, ExpandLds &X,
-                            Counts &c) {
+// warm: upper bounds of the coreness to start from, plus warm_add (nullptr:
+// start from the degrees).
+template <bool kLds, typename Off>
+__device__ void histo_graph(const TaskT<Off> &t, int sum_wave_min, WgCounters &w, ExpandLds &X,
+                            Counts &c, const int32_t *warm = nullptr, int warm_add = 0) {
     const int nv = t.n;
-    const long long *off = t.off;
+    const Off *off = t.off;
     const long long e0 = t.e0;
     Vals<kLds> cv{t.core};
     int32_t *out = t.out;
@@ -301,20 +313,29 @@ __device__ void histo_graph(const Task &t, int sum_wave_min, WgCounters &w, Expa
         w.a = 0;
         w.b = 0;
     }
-    for (int i = threadIdx.x; i < nv; i += kBlock) cv.set(i, (int)(off[i + 1] - off[i]));
+    for (int i = threadIdx.x; i < nv; i += kBlock) {
+        const int d = (int)(off[i + 1] - off[i]);
+        int v0 = d;
+        if (warm && d > 0) {
+            const long long b = (long long)warm[i] + warm_add;
+            v0 = (int)(b < 1 ? 1 : (b > d ? d : b));
+        }
+        cv.set(i, v0);
+    }
     for (long long e = threadIdx.x; e < m; e += kBlock) histo[e] = 0;
     __syncthreads();
     // InitHisto: bucket min(core[u], core[v]) of v counts neighbour u
     for (int base = 0; base < nv; base += kBlock) {
         const int i = base + (int)threadIdx.x;
         long long rs = 0;
-        int d = 0;
+        int d = 0, nb = 0;  // neighbours, buckets (the starting value)
         if (i < nv) {
             rs = off[i];
             d = (int)(off[i + 1] - rs);
+            nb = cv.get(i);
         }
         block_expand<kBatchRounds>(
-            d, rs, d, 0, t.cols, X,
+            d, rs, nb, 0, t.cols, X,
             [&](const bool (&act)[kBatchRounds], const int (&u)[kBatchRounds],
                 const int (&own)[kBatchRounds]) {
 #pragma unroll
@@ -580,9 +601,13 @@ __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shar
             st_rlx(&job->x.done, 0ull);
             // 16-bit sequence; 2^16 is even, so the parity survives the wrap
             const unsigned long long seq = ((ld_rlx(&job->x.ctl) >> 48) + 1) & 0xffffull;  // odd: open
-            fence_release();  // parameters and counters before the control word
+            // parameters and counters before the control word
             st_rel(&job->x.ctl, job_word(seq, (unsigned long long)nch, 0));
         }
+        // The counters this thread reset between phases must be in place
+        // before any wave of the workgroup adds to them: the barrier below
+        // does not wait for the stores.
+        wave_mem_drain();
     }
     __syncthreads();
     long long own = 0;
@@ -596,12 +621,14 @@ __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shar
         run_chunk(t, p, &job->n, c0, c1, X, c);
         ++own;
     }
-    // every wave's stores and atomics performed before the count below: the
-    // workgroup barrier does not wait for other waves' vector-memory traffic
-    fence_release();
+    // every wave's stores and atomics performed before the count below (the
+    // workgroup barrier does not wait for other waves' vector-memory traffic)
+    wave_mem_drain();
     __syncthreads();
     if (threadIdx.x == 0) {
         if (open) {
+            // (no release here: only this thread reads the count, and the next
+            // phase's control word publishes what this workgroup wrote)
             unsigned long long d = atomicAdd(&job->x.done, (unsigned long long)own) + own;
             const unsigned long long t0 = wall_clock64();
             while (d < (unsigned long long)nch) {  // chunks still being run by helpers
@@ -613,7 +640,7 @@ __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shar
                 d = ld_acq(&job->x.done);
             }
             const unsigned long long seq = ((ld_rlx(&job->x.ctl) >> 48) + 1) & 0xffffull;  // even: closed
-            st_rel(&job->x.ctl, job_word(seq, 0, 0));
+            st_rlx(&job->x.ctl, job_word(seq, 0, 0));  // publishes nothing
             fence_acquire();
         }
         sh.a = ld_rlx(&job->n.a);
@@ -694,7 +721,7 @@ __device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long t
     }
     c.frontier += peelable;
     if (threadIdx.x == 0) {
-        if (shared) st_rel(&a.st->open[slot], 0ull);
+        if (shared) st_rlx(&a.st->open[slot], 0ull);
         if (sh.err) atomicAdd(&a.st->stuck.v, 1ull);
         atomicAdd(&a.st->helped.v, shared ? 1ull : 0ull);
     }
@@ -753,9 +780,10 @@ __device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
         run_chunk(t, p, &job->n, c0, c1, X, c);
         // every wave's stores and atomics performed before the chunk is counted
         // (the workgroup barrier does not wait for vector-memory traffic)
-        fence_release();
+        wave_mem_drain();
         __syncthreads();
         if (threadIdx.x == 0) {
+            fence_release();
             atomicAdd(&job->x.done, 1ull);
             atomicAdd(&a.st->helpchunks.v, 1ull);
         }
@@ -763,7 +791,8 @@ __device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
 }
 
 // One graph, by the workgroup: LDS tier if its values fit.
-__device__ __forceinline__ void decompose(const Task &t, int algo, int lds_cap, int sum_wave_min,
+template <typename Off>
+__device__ __forceinline__ void decompose(const TaskT<Off> &t, int algo, int lds_cap, int sum_wave_min,
                                           WgCounters &w, ExpandLds &X, Counts &c) {
     if (t.n <= 0) return;
     const bool lds = t.n <= lds_cap;
@@ -813,6 +842,64 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
         if (c.frontier) atomicAdd(&a.st->frontier.v, (unsigned long long)c.frontier);
         if (c.lds) atomicAdd(&a.st->lds_graphs.v, (unsigned long long)c.lds);
     }
+}
+
+// ------------------------------------------------ one small graph
+//
+// A graph whose vertex values fit in one workgroup's LDS is decomposed by a
+// single workgroup: the same per-graph code as a batch, launched alone, with
+// workgroup barriers where the grid-wide kernels need grid barriers (a few
+// microseconds each on a full device, which decide small graphs).
+
+enum { SM_LEVELS = 0, SM_SCANS, SM_DRAINS, SM_KMAX, SM_FRONTIER, SM_ATOMICS, SM_EDGES, SM_BUCKETS,
+       SM_PUSHES, SM_WORDS };
+
+// The workgroup's counts into stats[SM_*] (plain stores by thread 0).
+__device__ void small_stats(const Counts &c, unsigned long long *stats) {
+    __shared__ long long part[kBlock / kWave][4];
+    const long long s_atom = wave_sum64(c.atomics), s_edges = wave_sum64(c.edges);
+    const long long s_buck = wave_sum64(c.buckets), s_push = wave_sum64(c.pushes);
+    if (lane_id() == 0) {
+        const int wv = (int)threadIdx.x / kWave;
+        part[wv][0] = s_atom;
+        part[wv][1] = s_edges;
+        part[wv][2] = s_buck;
+        part[wv][3] = s_push;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t[4] = {0, 0, 0, 0};
+        for (int wv = 0; wv < kBlock / kWave; ++wv)
+            for (int j = 0; j < 4; ++j) t[j] += part[wv][j];
+        stats[SM_LEVELS] = (unsigned long long)c.levels;
+        stats[SM_SCANS] = (unsigned long long)c.scans;
+        stats[SM_DRAINS] = (unsigned long long)c.drains;
+        stats[SM_KMAX] = (unsigned long long)c.kmax;
+        stats[SM_FRONTIER] = (unsigned long long)c.frontier;
+        stats[SM_ATOMICS] = (unsigned long long)t[0];
+        stats[SM_EDGES] = (unsigned long long)t[1];
+        stats[SM_BUCKETS] = (unsigned long long)t[2];
+        stats[SM_PUSHES] = (unsigned long long)t[3];
+    }
+}
+
+template <typename Off>
+__global__ __launch_bounds__(kBlock) void po_small(TaskT<Off> t, unsigned long long *stats) {
+    __shared__ WgCounters w;
+    __shared__ ExpandLds X;
+    Counts c;
+    peel_graph<true>(t, w, X, c);
+    small_stats(c, stats);
+}
+
+template <typename Off>
+__global__ __launch_bounds__(kBlock) void hc_small(TaskT<Off> t, int sum_wave_min, const int32_t *warm,
+                                                    int warm_add, unsigned long long *stats) {
+    __shared__ WgCounters w;
+    __shared__ ExpandLds X;
+    Counts c;
+    histo_graph<true>(t, sum_wave_min, w, X, c, warm, warm_add);
+    small_stats(c, stats);
 }
 
 __global__ void batch_state_init(BatchState *st) {
@@ -972,6 +1059,143 @@ int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune
 }
 
 }  // namespace
+
+// ------------------------------------------------ one small graph (host)
+
+namespace {
+
+// Dynamic LDS one workgroup of `kernel` may take (bytes), its launch limit
+// raised to that once per kernel.
+int small_lds_cap(const void *kernel, int *cap) {
+    static std::mutex mu;
+    static const void *keys[4] = {nullptr, nullptr, nullptr, nullptr};
+    static int caps[4] = {0, 0, 0, 0};
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < 4; ++i)
+        if (keys[i] == kernel) {
+            *cap = caps[i];
+            return PICO_OK;
+        }
+    int dev = 0, max_dyn = 0;
+    PICO_HIP_TRY(hipGetDevice(&dev));
+    PICO_HIP_TRY(hipDeviceGetAttribute(&max_dyn, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    hipFuncAttributes fa;
+    PICO_HIP_TRY(hipFuncGetAttributes(&fa, kernel));
+    int c = (max_dyn - (int)fa.sharedSizeBytes) & ~255;
+    if (c < 0) c = 0;
+    if (c > 48 * 1024) PICO_HIP_TRY(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, c));
+    for (int i = 0; i < 4; ++i)
+        if (!keys[i]) {
+            keys[i] = kernel;
+            caps[i] = c;
+            break;
+        }
+    *cap = c;
+    return PICO_OK;
+}
+
+template <typename Off>
+const void *small_kernel(int algo) {
+    return (algo & PICO_ALGO_MASK) == PICO_ALGO_HISTOCORE ? reinterpret_cast<const void *>(hc_small<Off>)
+                                                          : reinterpret_cast<const void *>(po_small<Off>);
+}
+
+// Largest m the one-workgroup path takes by default (PICO_SMALL_MAX_EDGES
+// overrides; 0 turns the default path off).
+long long small_max_edges() {
+    static long long v = -1;
+    if (v < 0) {
+        const char *e = getenv("PICO_SMALL_MAX_EDGES");
+        v = (e && *e && atoll(e) >= 0) ? atoll(e) : kSmallMaxEdgesDefault;
+    }
+    return v;
+}
+
+}  // namespace
+
+size_t small_ws_bytes(int64_t n, int64_t m, int algo) {
+    size_t b = carve_bytes(n, 4) * 4 + carve_bytes(SM_WORDS, 8);
+    if ((algo & PICO_ALGO_MASK) == PICO_ALGO_HISTOCORE) b += carve_bytes(n, 4) + carve_bytes(m, 4);
+    return b;
+}
+
+int small_path(int64_t n, int64_t m, int algo, bool *use) {
+    *use = false;
+    if (algo & PICO_PATH_GRID) return PICO_OK;
+    const bool forced = (algo & PICO_PATH_WG) != 0;
+    if (!forced && m > small_max_edges()) return PICO_OK;
+    int cap = 0;
+    const bool i64 = (algo & PICO_OFFSETS_I64) != 0;
+    int rc = small_lds_cap(i64 ? small_kernel<int64_t>(algo) : small_kernel<int32_t>(algo), &cap);
+    if (rc) return rc;
+    if (n * 4 > (int64_t)cap) {
+        if (forced) {
+            set_error("PICO_PATH_WG: %lld vertex values need %lld bytes of LDS, %d available",
+                      (long long)n, (long long)n * 4, cap);
+            return PICO_ENOTSUP;
+        }
+        return PICO_OK;
+    }
+    *use = true;
+    return PICO_OK;
+}
+
+template <typename Off>
+int run_small(const Off *off, const int32_t *cols, int64_t n, int64_t m, int algo, int32_t *out,
+              void *ws, size_t ws_bytes, pico_stats *stats, hipStream_t stream, const int32_t *warm,
+              int warm_add) {
+    const bool hc = (algo & PICO_ALGO_MASK) == PICO_ALGO_HISTOCORE;
+    Carve cv{static_cast<char *>(ws), 0, ws_bytes};
+    TaskT<Off> t;
+    t.off = off;
+    t.cols = cols;
+    t.e0 = 0;
+    t.n = (int)n;
+    t.pad = 0;
+    t.out = out;
+    t.core = cv.take<int32_t>(n);  // values live in LDS; unused
+    t.L0 = cv.take<int32_t>(n);
+    t.L1 = cv.take<int32_t>(n);
+    t.L2 = cv.take<int32_t>(n);
+    t.oldcore = hc ? cv.take<int32_t>(n) : nullptr;
+    t.histo = hc ? cv.take<int32_t>(m) : nullptr;
+    unsigned long long *sm = cv.take<unsigned long long>(SM_WORDS);
+    if (!t.core || !t.L0 || !t.L1 || !t.L2 || !sm || (hc && (!t.oldcore || !t.histo))) {
+        set_error("workspace too small for the one-workgroup path (%zu bytes given, %zu needed)", ws_bytes,
+                  small_ws_bytes(n, m, algo));
+        return PICO_ENOMEM;
+    }
+    const size_t lds = (size_t)n * 4;
+    int rec = prof_begin(hc ? "hc_small" : "po_small", stream);
+    if (hc)
+        hipLaunchKernelGGL(hc_small<Off>, dim3(1), dim3(kBlock), lds, stream, t, kSumWaveMinDefault, warm,
+                           warm_add, sm);
+    else
+        hipLaunchKernelGGL(po_small<Off>, dim3(1), dim3(kBlock), lds, stream, t, sm);
+    prof_end(rec, stream);
+    PICO_LAUNCH_CHECK();
+    if (stats) {
+        unsigned long long *h = static_cast<unsigned long long *>(host_scratch(SM_WORDS * 8));
+        if (!h) return PICO_EHIP;
+        PICO_HIP_TRY(hipMemcpyAsync(h, sm, SM_WORDS * 8, hipMemcpyDeviceToHost, stream));
+        PICO_HIP_TRY(hipStreamSynchronize(stream));
+        stats->iterations = (int64_t)h[SM_LEVELS];
+        stats->sub_rounds = hc ? (int64_t)h[SM_LEVELS] : (int64_t)h[SM_DRAINS];
+        stats->scans = hc ? 0 : (int64_t)h[SM_SCANS];
+        stats->frontier_total = (int64_t)h[SM_FRONTIER];
+        stats->k_max = hc ? 0 : (int32_t)h[SM_KMAX];
+        stats->edges_scanned = (int64_t)h[SM_EDGES];
+        stats->atomics = (int64_t)h[SM_ATOMICS];
+        stats->buckets_scanned = (int64_t)h[SM_BUCKETS];
+        stats->pushes_dynamic = (int64_t)h[SM_PUSHES];
+    }
+    return PICO_OK;
+}
+
+template int run_small<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int, int32_t *, void *,
+                                size_t, pico_stats *, hipStream_t, const int32_t *, int);
+template int run_small<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int, int32_t *, void *,
+                                size_t, pico_stats *, hipStream_t, const int32_t *, int);
 
 size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo) {
     size_t b = carve_bytes(total_n, 4) * 4 + carve_bytes(1, sizeof(BatchState)) +

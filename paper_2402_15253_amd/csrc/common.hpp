@@ -101,18 +101,7 @@ __device__ __forceinline__ void st_rlx(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
-__device__ __forceinline__ void st_rel(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ T fadd_rel(T *p, T v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ bool cas_acq_rel(T *p, T expected, T desired) {
-    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ void st_rel(T *p, T v);  // release fence, then a relaxed store
 
 // A counter alone on its cache lines, so hot counters do not share a line.
 struct alignas(128) Line {
@@ -171,8 +160,24 @@ struct NoRelease {
     __device__ void operator()(GridState *) const {}
 };
 
+// Wait until this wave's outstanding memory operations (vector loads,
+// stores and atomics; scalar and LDS traffic) have completed.
+__device__ __forceinline__ void wave_mem_drain() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Agent-scope release: the fence writes back this XCD's L2 (buffer_wbl2),
+// and the explicit wait makes the write-back complete before whatever
+// follows.  The compiler's own wait after the write-back is dropped when the
+// wave has no other memory operation outstanding (it does not count the
+// write-back as one), and then the signal after the fence could reach memory
+// before the data it publishes.
 __device__ __forceinline__ void fence_release() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
+}
+template <typename T>
+__device__ __forceinline__ void st_rel(T *p, T v) {
+    fence_release();
+    st_rlx(p, v);
 }
 __device__ __forceinline__ void fence_acquire() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -195,9 +200,10 @@ template <int NSNAP = kNumCtr, typename Rel = NoRelease>
 __device__ __forceinline__ bool grid_sync(GridState *gs, unsigned nblocks, unsigned long long limit,
                                           unsigned long long *snap_out, unsigned long long &bar_no,
                                           Rel on_release = Rel()) {
-    // every wave's stores and atomics are performed before the block arrives:
-    // the workgroup barrier waits for LDS traffic only
-    fence_release();
+    // every wave's stores and atomics are performed before the block arrives
+    // (the workgroup barrier waits for LDS traffic only); thread 0's release
+    // fence below then writes them back from this XCD's L2
+    wave_mem_drain();
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned ngroups = nblocks < (unsigned)kBarGroups ? nblocks : (unsigned)kBarGroups;
@@ -535,10 +541,20 @@ inline size_t carve_bytes(int64_t count, size_t elem) {
 // Small pinned host buffer for counter read-back (one per host thread).
 void *host_scratch(size_t bytes);
 
-// Cooperative launch of a persistent kernel with the largest co-resident grid
-// (capped at `max_per_cu` blocks per compute unit).  Returns the grid size
-// used in *blocks.
-int persistent_grid(const void *kernel, int block, int max_per_cu, int *blocks);
+// Cooperative launch of a persistent kernel: the largest co-resident grid
+// (capped at `max_per_cu` blocks per compute unit), or `want` blocks if that
+// is smaller (want <= 0: no cap).  Returns the grid size used in *blocks.
+int persistent_grid(const void *kernel, int block, int max_per_cu, long long want, int *blocks);
+
+// Workgroups a persistent launch asks for on a graph of m entries (0: the
+// whole device).  Below a few million entries the grid barriers, not the
+// edge work, decide the time, and a smaller grid makes each barrier cheaper.
+// The bounds come from a sweep of grid sizes on MI355X over ER and R-MAT
+// graphs of 8 thousand to 7.6 million entries (PeelOne best at 16-64
+// workgroups there, HistoCore at about m / 2048 up to one per CU).
+inline long long clamp_ll(long long x, long long lo, long long hi) { return x < lo ? lo : (x > hi ? hi : x); }
+inline long long grid_want_peelone(int64_t m) { return m >= (1ll << 23) ? 0 : clamp_ll(m >> 14, 16, 64); }
+inline long long grid_want_histocore(int64_t m) { return m >= (1ll << 23) ? 0 : clamp_ll(m >> 11, 8, 256); }
 
 // Wall-clock ticks for `seconds` (device wall clock rate).
 unsigned long long wall_ticks(double seconds);
@@ -561,14 +577,21 @@ void prof_end(int rec, hipStream_t s);
 size_t peelone_ws_bytes(int64_t n, int64_t m);
 size_t histocore_ws_bytes(int64_t n, int64_t m);
 
-// err_async (pinned host word) set: enqueue the kernel and a copy of its
-// error word there, and return without waiting; NULL: wait and report.
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
-                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream,
-                unsigned long long *err_async = nullptr);
+                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream);
 
 size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo);
+
+// One graph by one workgroup, vertex values in LDS (graphs small enough that
+// grid barriers would dominate).  small_path decides from n, m and the path
+// flags of algo; run_small runs it.
+size_t small_ws_bytes(int64_t n, int64_t m, int algo);
+int small_path(int64_t n, int64_t m, int algo, bool *use);
+template <typename Off>
+int run_small(const Off *off, const int32_t *cols, int64_t n, int64_t m, int algo, int32_t *out,
+              void *ws, size_t ws_bytes, pico_stats *stats, hipStream_t stream,
+              const int32_t *warm = nullptr, int warm_add = 0);
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo);
 size_t tasks_ws_bytes(int64_t T);
 pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T);
@@ -588,10 +611,12 @@ int run_batched(const long long *vptr, const long long *off, const int32_t *cols
                 void *ws, size_t ws_bytes, const pico_batch_tune *tune, pico_batch_stats *stats,
                 hipStream_t stream);
 
+// warm (optional): start from these upper bounds of the coreness, plus
+// warm_add, instead of the degrees.
 template <typename Off>
 int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
                   void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream,
-                  unsigned long long *err_async = nullptr);
+                  const int32_t *warm = nullptr, int warm_add = 0);
 
 inline int grid_for(int64_t items_per_block_units, int cap) {
     int64_t g = items_per_block_units;

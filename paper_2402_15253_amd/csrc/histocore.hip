@@ -79,6 +79,8 @@ struct HcArgs {
     long long hcap;
     HcState *st;
     unsigned long long limit;
+    const int32_t *warm;  // upper bounds of the coreness to start from (nullptr: the degrees)
+    int warm_add;         // added to every bound
 };
 
 inline long long pieces_cap(int64_t m) { return m / kInitCh + m / kLdsCap + 64; }
@@ -141,40 +143,43 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
          tile += (long long)gridDim.x * kBlock) {
         long long v = tile + threadIdx.x;
         bool valid = v < a.n;
-        int d = valid ? a.core[v] : 0;
+        // c: v's starting value, its number of buckets; d: its neighbours
+        // (equal unless the run starts from given bounds)
+        int c = valid ? a.core[v] : 0;
         long long e0 = valid ? (long long)a.off[v] : 0;
+        int d = valid && a.warm ? (int)((long long)a.off[v + 1] - e0) : c;
         bool push = false;
         if (valid && d > 0 && d <= kSmall) {
             // one lane owns v's segment: plain read-modify-write, no atomics
-            for (int j = 0; j < d; ++j) a.histo[e0 + j] = 0;
+            for (int j = 0; j < c; ++j) a.histo[e0 + j] = 0;
             for (int j = 0; j < d; ++j) {
                 int u = a.cols[e0 + j];
                 int du = a.core[u];
                 a.ndeg[e0 + j] = du;
-                int b = min(max(du, 1), d);  // core[u] >= 1 on a symmetric graph
+                int b = min(max(du, 1), c);  // core[u] >= 1 on a symmetric graph
                 a.histo[e0 + b - 1] += 1;
             }
-            push = a.histo[e0 + d - 1] < d;
+            push = a.histo[e0 + c - 1] < c;
         }
         unsigned long long mm = __ballot(valid && d > kSmall && d <= kLdsCap);
         while (mm) {
             int l = __ffsll(mm) - 1;
             mm &= mm - 1;
-            int dd = __shfl(d, l);
+            int dd = __shfl(d, l), cc = __shfl(c, l);
             long long ea = __shfl(e0, l);
-            for (int j = lane; j < dd; j += kWave) lds[j] = 0;
+            for (int j = lane; j < cc; j += kWave) lds[j] = 0;
             wave_lds_sync();
             for (int j = lane; j < dd; j += kWave) {
                 int u = a.cols[ea + j];
                 int du = a.core[u];
                 a.ndeg[ea + j] = du;
-                atomicAdd(&lds[min(max(du, 1), dd) - 1], 1);
+                atomicAdd(&lds[min(max(du, 1), cc) - 1], 1);
             }
             wave_lds_sync();
-            for (int j = lane; j < dd; j += kWave) a.histo[ea + j] = lds[j];
-            int top = lds[dd - 1];
+            for (int j = lane; j < cc; j += kWave) a.histo[ea + j] = lds[j];
+            int top = lds[cc - 1];
             wave_lds_sync();
-            if (lane == l) push = top < dd;
+            if (lane == l) push = top < cc;
         }
         int tot = 0;
         long long etot = 0;
@@ -214,7 +219,7 @@ __device__ void init_heavy(const HcArgs<Off> &a, unsigned long long h0, unsigned
         int v = (int)(desc >> 32);
         long long j = desc & 0xffffffffll;
         long long vb = (long long)a.off[v], ve = (long long)a.off[v + 1];
-        int d = (int)(ve - vb);
+        const int c = a.core[v];  // buckets (the degree unless started from bounds)
         long long e0 = vb + j * kInitCh, e1 = e0 + kInitCh < ve ? e0 + kInitCh : ve;
         for (long long e = e0 + lane_id(); e < e1; e += kWave) {
             if (pass == 0) {
@@ -223,7 +228,7 @@ __device__ void init_heavy(const HcArgs<Off> &a, unsigned long long h0, unsigned
                 int u = a.cols[e];
                 int du = a.core[u];
                 a.ndeg[e] = du;
-                atomicAdd(&a.histo[vb + min(max(du, 1), d) - 1], 1);
+                atomicAdd(&a.histo[vb + min(max(du, 1), c) - 1], 1);
             }
         }
     }
@@ -241,9 +246,10 @@ __device__ void init_heavy_check(const HcArgs<Off> &a, unsigned long long s0, un
         long long rs = 0;
         if (i < (long long)s1) {
             v = a.HS[i % a.n];
-            d = a.core[v];
+            const int c = a.core[v];
             rs = (long long)a.off[v];
-            push = a.histo[rs + d - 1] < d;
+            d = (int)((long long)a.off[v + 1] - rs);  // the row, for the round's edge space
+            push = a.histo[rs + c - 1] < c;
         }
         wave_push_packed(push, v, rs, d, &gs->ctr[FET].v, 0, a.F[0], a.FE[0], a.FR[0]);
     }
@@ -433,9 +439,18 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
     PhaseClock clk;
     if (timer) clk.start();
 
+    // core = deg, or the given upper bound capped by the degree (at least 1
+    // on a vertex with neighbours, whose coreness is at least 1)
     for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < a.n;
-         v += (long long)gridDim.x * kBlock)
-        a.core[v] = (int)(a.off[v + 1] - a.off[v]);
+         v += (long long)gridDim.x * kBlock) {
+        const int d = (int)(a.off[v + 1] - a.off[v]);
+        int c = d;
+        if (a.warm && d > 0) {
+            const long long w = (long long)a.warm[v] + a.warm_add;
+            c = (int)(w < 1 ? 1 : (w > d ? d : w));
+        }
+        a.core[v] = c;
+    }
     if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[0].v);
     init_histo<Off>(a, lds_all[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64);
@@ -508,7 +523,8 @@ size_t histocore_ws_bytes(int64_t n, int64_t m) {
 
 template <typename Off>
 int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
-                  size_t ws_bytes, pico_stats *stats, hipStream_t stream, unsigned long long *err_async) {
+                  size_t ws_bytes, pico_stats *stats, hipStream_t stream, const int32_t *warm,
+                  int warm_add) {
     if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
         set_error("m=%lld too large for the packed frontier counter", (long long)m);
         return PICO_ENOTSUP;
@@ -540,9 +556,11 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
         return PICO_ENOMEM;
     }
     a.limit = wall_ticks(20.0);
+    a.warm = warm;
+    a.warm_add = warm_add;
     int blocks = 0;
     int rc = persistent_grid(reinterpret_cast<const void *>(hc_persistent<Off>), kBlock,
-                             tune_int("PICO_HC_BLOCKS_PER_CU", 2), &blocks);
+                             tune_int("PICO_HC_BLOCKS_PER_CU", 2), grid_want_histocore(m), &blocks);
     if (rc) return rc;
     PICO_LAUNCH("hc_state_init", hc_state_init, dim3(1), dim3(kBlock), stream, a.st);
     PICO_LAUNCH_CHECK();
@@ -551,11 +569,6 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
     PICO_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(hc_persistent<Off>),
                                             dim3(blocks), dim3(kBlock), args, 0, stream));
     prof_end(rec, stream);
-    if (err_async) {  // the caller checks the error word once the stream is done
-        PICO_HIP_TRY(hipMemcpyAsync(err_async, &a.st->g.error.v, sizeof(unsigned long long),
-                                    hipMemcpyDeviceToHost, stream));
-        return PICO_OK;
-    }
     HcState *h = static_cast<HcState *>(host_scratch(sizeof(HcState)));
     if (!h) return PICO_EHIP;
     PICO_HIP_TRY(hipMemcpyAsync(h, a.st, sizeof(HcState), hipMemcpyDeviceToHost, stream));
@@ -582,8 +595,8 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
 }
 
 template int run_histocore<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                    void *, size_t, pico_stats *, hipStream_t, unsigned long long *);
+                                    void *, size_t, pico_stats *, hipStream_t, const int32_t *, int);
 template int run_histocore<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                    void *, size_t, pico_stats *, hipStream_t, unsigned long long *);
+                                    void *, size_t, pico_stats *, hipStream_t, const int32_t *, int);
 
 }  // namespace pico

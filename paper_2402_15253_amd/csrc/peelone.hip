@@ -500,7 +500,7 @@ size_t peelone_ws_bytes(int64_t n, int64_t m) {
 
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
-                size_t ws_bytes, pico_stats *stats, hipStream_t stream, unsigned long long *err_async) {
+                size_t ws_bytes, pico_stats *stats, hipStream_t stream) {
     if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
         set_error("m=%lld too large for the packed frontier counter", (long long)m);
         return PICO_ENOTSUP;
@@ -526,7 +526,7 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     a.limit = wall_ticks(20.0);
     a.trace = nullptr;
     a.trace_cap = 0;
-    const char *trace_file = err_async ? nullptr : getenv("PICO_TRACE_FILE");  // development aid
+    const char *trace_file = getenv("PICO_TRACE_FILE");  // development aid
     if (trace_file && *trace_file) {
         a.trace_cap = 1 << 14;
         PICO_HIP_TRY(hipMallocAsync((void **)&a.trace, sizeof(long long) * 8 * a.trace_cap, stream));
@@ -538,7 +538,7 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     // more gather latency (RMAT-26: 142 ms at one, 133.5 at two, 137.7 at four).
     const int per_cu_default = m >= (1ll << 28) ? 2 : 1;
     int rc = persistent_grid(reinterpret_cast<const void *>(po_persistent<Off>), kBlock,
-                             tune_int("PICO_PO_BLOCKS_PER_CU", per_cu_default), &blocks);
+                             tune_int("PICO_PO_BLOCKS_PER_CU", per_cu_default), grid_want_peelone(m), &blocks);
     if (rc) return rc;
     PICO_LAUNCH("po_state_init", po_state_init, dim3(1), dim3(kBlock), stream, a.st);
     PICO_LAUNCH_CHECK();
@@ -547,11 +547,6 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     PICO_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(po_persistent<Off>),
                                             dim3(blocks), dim3(kBlock), args, 0, stream));
     prof_end(rec, stream);
-    if (err_async) {  // the caller checks the error word once the stream is done
-        PICO_HIP_TRY(hipMemcpyAsync(err_async, &a.st->g.error.v, sizeof(unsigned long long),
-                                    hipMemcpyDeviceToHost, stream));
-        return PICO_OK;
-    }
 
     PoState *h = static_cast<PoState *>(host_scratch(sizeof(PoState)));
     if (!h) return PICO_EHIP;
@@ -597,8 +592,8 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
 }
 
 template int run_peelone<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                  void *, size_t, pico_stats *, hipStream_t, unsigned long long *);
+                                  void *, size_t, pico_stats *, hipStream_t);
 template int run_peelone<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                  void *, size_t, pico_stats *, hipStream_t, unsigned long long *);
+                                  void *, size_t, pico_stats *, hipStream_t);
 
 }  // namespace pico

@@ -33,6 +33,8 @@ KERNEL_SOURCES = {
     "po_persistent": ("peelone.hip", "common.hpp"),
     "hc_persistent": ("histocore.hip", "common.hpp"),
     "batched_kernel": ("batched.hip", "common.hpp"),
+    "po_small": ("batched.hip", "common.hpp"),
+    "hc_small": ("batched.hip", "common.hpp"),
 }
 KERNELS = tuple(KERNEL_SOURCES)
 COPY_KERNEL = "__amd_rocclr_copyBuffer"

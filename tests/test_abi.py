@@ -52,6 +52,25 @@ def test_argument_errors_need_no_device():
     assert pico.pico_coreness(None, None, 0, 0, 7, None) == pico.PICO_EINVAL
     assert pico.pico_coreness(None, None, 0, 0, 0, None) == pico.PICO_OK  # n == 0: no-op
     assert pico.pico_coreness_ws(None, None, 0, 0, 1, None, None, 0) == pico.PICO_OK
+    # path flags: one at a time, single-graph calls only
+    both = pico.PICO_PATH_GRID | pico.PICO_PATH_WG
+    assert pico.pico_coreness(None, None, 0, 0, both, None) == pico.PICO_EINVAL
+    assert "exclusive" in pico.pico_last_error()
+    assert pico.pico_coreness(None, None, 0, 0, pico.PICO_PATH_WG, None) == pico.PICO_OK
+    assert pico.pico_coreness(None, None, 0, 0, 0x800, None) == pico.PICO_EINVAL
+    # core maintenance: HistoCore only, bounds required, bound_add >= 0
+    up = pico.pico_coreness_update
+    hc = pico.PICO_ALGO_HISTOCORE
+    assert up(None, None, 0, 0, pico.PICO_ALGO_PEELONE, None, 0, None, None, 0) == pico.PICO_ENOTSUP
+    assert up(None, None, 0, 0, hc, None, -1, None, None, 0) == pico.PICO_EINVAL
+    assert up(None, None, 10, 0, hc, None, 0, None, None, 0) == pico.PICO_EINVAL
+    assert "prev_core" in pico.pico_last_error()
+    assert up(None, None, 0, 0, hc, None, 0, None, None, 0) == pico.PICO_OK  # n == 0: no-op
+    # a workspace sized without a path flag serves either path
+    for algo in (pico.PICO_ALGO_PEELONE, pico.PICO_ALGO_HISTOCORE):
+        auto = pico.pico_workspace_bytes(5000, 40000, algo)
+        assert auto == pico.pico_workspace_bytes(5000, 40000, algo | pico.PICO_PATH_GRID)
+        assert auto == pico.pico_workspace_bytes(5000, 40000, algo | pico.PICO_PATH_WG)
 
 
 def test_task_and_server_argument_checks_need_no_device():

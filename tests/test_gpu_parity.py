@@ -23,18 +23,18 @@ def _gpu(g):
     return g.to("cuda")
 
 
-def _run(g, algo, with_stats=False):
+def _run(g, algo, with_stats=False, path=None):
     d = _gpu(g)
-    res = pico.coreness(d.offsets, d.cols, algo, with_stats=with_stats)
+    res = pico.coreness(d.offsets, d.cols, algo, with_stats=with_stats, path=path)
     torch.cuda.synchronize()
     if with_stats:
         return res[0].cpu().numpy(), res[1]
     return res.cpu().numpy()
 
 
-def _check(g, algo):
+def _check(g, algo, path=None):
     want = oracle.bz_coreness(g.offsets, g.cols)
-    got, st = _run(g, algo, with_stats=True)
+    got, st = _run(g, algo, with_stats=True, path=path)
     assert got.dtype == np.int32 and got.shape == (g.n,)
     mism = np.nonzero(got != want)[0]
     assert mism.size == 0, f"{g.name} {algo}: {mism.size} mismatches, first {mism[:5]} " \
@@ -57,12 +57,53 @@ SMALL_CASES = [
 ]
 
 
+# values of up to this many vertices fit in one workgroup's LDS on gfx950
+WG_FITS = 32768
+
+
+@pytest.mark.parametrize("path", ["grid", "wg"])
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("case", range(len(SMALL_CASES)))
-def test_closed_forms_and_edge_cases(algo, case):
+def test_closed_forms_and_edge_cases(algo, case, path):
     g = SMALL_CASES[case]()
-    print(f"case {g.name} n={g.n} m={g.m} algo={algo}", flush=True)
-    _check(g, algo)
+    print(f"case {g.name} n={g.n} m={g.m} algo={algo} path={path}", flush=True)
+    if path == "wg" and g.n > 2 * WG_FITS:
+        with pytest.raises(pico.PicoError) as e:
+            _run(g, algo, path=path)
+        assert e.value.status == pico.PICO_ENOTSUP
+        return
+    _check(g, algo, path)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_large_clique_one_workgroup(algo):
+    g = gg.complete(2000)  # 4M entries, far above the default bound of the path
+    got = _run(g, algo, path="wg")
+    assert (got == 1999).all()
+
+
+@pytest.mark.parametrize("offsets_dtype", [torch.int32, torch.int64])
+def test_paths_agree_on_schedule(offsets_dtype):
+    """The one-workgroup and grid paths report the same schedule where it is
+    fixed by the graph: PeelOne's levels, peeled and asserted vertices and
+    k_max; HistoCore's rounds, frontier sizes, edges scanned and histogram
+    moves (Theorem 2 fixes the synchronous rounds).  Scan counts may differ
+    by one: the grid path ends with a scan that finds no survivor when the
+    last level's survivors were all asserted during its drain."""
+    g = gg.rmat(13, 16, 21).with_offsets(offsets_dtype)
+    print(f"case {g.name} n={g.n} m={g.m} {offsets_dtype}", flush=True)
+    for algo, keys in (("peelone", ("iterations", "frontier_total", "k_max", "pushes_dynamic",
+                                    "edges_scanned")),
+                       ("histocore", ("iterations", "frontier_total", "edges_scanned", "atomics",
+                                      "pushes_dynamic"))):
+        _, st_wg = _check(g, algo, "wg")
+        _, st_grid = _check(g, algo, "grid")
+        _, st_auto = _check(g, algo, None)  # the library's choice by size (here the grid)
+        for k in keys:
+            assert st_wg[k] == st_grid[k] == st_auto[k], (algo, k, st_wg[k], st_grid[k], st_auto[k])
+        if algo == "peelone":
+            assert st_auto["scans"] == st_grid["scans"]
+            assert st_wg["scans"] <= st_grid["scans"] <= st_wg["scans"] + 1
 
 
 @pytest.mark.parametrize("algo", ALGOS)
@@ -79,14 +120,27 @@ def test_long_path(algo):
     assert (got == 1).all()
 
 
-def test_er10k_both_and_schedules():
+@pytest.mark.parametrize("blocks", [1, 3, 7, 13, 100])
+def test_grid_path_any_grid_size(blocks, monkeypatch):
+    """The persistent kernels are correct on any grid, including fewer
+    workgroups than barrier groups (the library picks small grids for small
+    graphs; PICO_GRID_BLOCKS forces one)."""
+    monkeypatch.setenv("PICO_GRID_BLOCKS", str(blocks))
+    g = gg.rmat(13, 16, 17)
+    print(f"case {g.name} n={g.n} m={g.m} blocks={blocks}", flush=True)
+    for algo in ALGOS:
+        _check(g, algo, "grid")
+
+
+@pytest.mark.parametrize("path", [None, "grid"])
+def test_er10k_both_and_schedules(path):
     g = gg.er_10k()
-    want, st_po = _check(g, "peelone")
+    want, st_po = _check(g, "peelone", path)
     levels = len(np.unique(want[want > 0]))
     assert st_po["iterations"] == levels
     assert st_po["frontier_total"] == int((want > 0).sum())
     assert st_po["k_max"] == int(want.max())
-    _, st_hc = _check(g, "histocore")
+    _, st_hc = _check(g, "histocore", path)
     _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
     assert st_hc["iterations"] == len(per_round)
     assert st_hc["frontier_total"] == sum(per_round)
@@ -107,10 +161,11 @@ def test_rmat_block_deep_hierarchy(algo):
     _check(g, algo)
 
 
-def test_histocore_round_sizes_match_jacobi():
+@pytest.mark.parametrize("path", ["grid", "wg"])
+def test_histocore_round_sizes_match_jacobi(path):
     g = gg.rmat(13, 16, 8)
     _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
-    _, st = _check(g, "histocore")
+    _, st = _check(g, "histocore", path)
     assert st["iterations"] == len(per_round)
     assert st["frontier_total"] == sum(per_round)
 
