@@ -521,6 +521,12 @@ def bench_update(args, pico, torch, np):
         if first is None:
             first = (name, h, rec)
     name, h, rec = first
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cpu = None
     if args.cpu_budget > 0:
         want, runs, t_cpu = cpu_baseline(h, args.cpu_budget)
@@ -564,6 +570,8 @@ def main():
                     help="after timing, copy 1 GiB device to device (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not bracket kernels with HIP events during the timed steps")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="single graphs: skip the PeelOne ablation runs after the timed steps")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched: skip the autotuner and use the default launch parameters")
     ap.add_argument("--graphs", type=int, default=4096, help="batched: number of graphs")
@@ -663,6 +671,26 @@ def main():
                     "kernel": kname, "avg_launch_ms": pk["avg_ms"],
                     "algorithmic_bytes_per_launch": pk["alg_bytes"]}
 
+    # Ablations of PeelOne (outside the timed region): what the dynamic
+    # frontier and the assertion decrement save (Tables IV and V).
+    ablations = None
+    if not args.no_ablations and "peelone" in algos:
+        ablations = {}
+        for variant in ("peelone", "peelone-static", "peelone-rollback"):
+            code = pico.algo_code(variant, g.offsets)
+            vout = torch.empty(n, dtype=torch.int32, device=dev)
+            vst = pico.PicoStats()
+            times = []
+            for _ in range(3):
+                rc = pico.pico_coreness_ws(g.offsets, g.cols, n, m, code, vout, ws, ws_bytes, vst, stream)
+                if rc != pico.PICO_OK:
+                    raise pico.PicoError(rc, pico.pico_last_error())
+                times.append(vst.elapsed_ms)
+            ablations[variant] = {"ms": round(min(times), 3), "iterations": vst.iterations,
+                                  "atomics": vst.atomics, "pushes_dynamic": vst.pushes_dynamic,
+                                  "identical": bool(torch.equal(vout, outs["peelone"]))}
+        log(f"ablations: {ablations}")
+
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -678,6 +706,9 @@ def main():
             props[f"{k}:{name}"] = ok
     if len(algos) == 2:
         props["peelone==histocore"] = bool(torch.equal(outs["peelone"], outs["histocore"]))
+    if ablations:
+        for variant, rec in ablations.items():
+            props[f"{variant}==peelone"] = rec["identical"]
     want = None
     cpu = None
     if args.cpu_budget > 0:
@@ -715,6 +746,7 @@ def main():
         "per_algo_gteps": {k: round(m / (v / args.steps / 1e3) / 1e9, 3)
                            for k, v in per_algo_ms.items()},
         "kernels": per_kernel,
+        "ablations": ablations,
         "levels_l1": st.get("peelone", {}).get("iterations"),
         "rounds_l2": st.get("histocore", {}).get("iterations"),
         "k_max": int(next(iter(outs.values())).max().item()) if n else 0,

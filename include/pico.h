@@ -61,6 +61,8 @@ typedef enum pico_status {
 enum {
     PICO_ALGO_PEELONE = 0,
     PICO_ALGO_HISTOCORE = 1,
+    PICO_ALGO_AUTO = 2,       /* single-graph calls: PeelOne or HistoCore, chosen per
+                                 graph by pico_select_algorithm's rule */
     PICO_ALGO_MASK = 0xff,
     PICO_OFFSETS_I64 = 0x100, /* OR-ed into algo: csr_offsets is int64[n+1] */
     /* Path selection, OR-ed into algo (single-graph calls only; at most one).
@@ -71,8 +73,19 @@ enum {
      * kernels.  Both paths compute the same coreness and statistics (the
      * per-phase times in phase_ms are grid-path only). */
     PICO_PATH_GRID = 0x200,   /* always the grid-wide persistent kernels */
-    PICO_PATH_WG = 0x400      /* always one workgroup; PICO_ENOTSUP if the
+    PICO_PATH_WG = 0x400,     /* always one workgroup; PICO_ENOTSUP if the
                                  values do not fit in its LDS */
+    /* Ablations of PeelOne, OR-ed into PICO_ALGO_PEELONE (single-graph calls,
+     * grid path; at most one).  Same coreness; they exist to measure what
+     * Alg. 4's mechanisms save (Section III, Tables IV and V).
+     *   PICO_PO_STATIC: no dynamic frontier -- a vertex lowered to k waits
+     *     for the next scan at level k; stats.iterations then counts every
+     *     iteration (Table IV's l1 for this variant).
+     *   PICO_PO_ROLLBACK: the decrement of atomicAdd-rollback methods
+     *     (Section III-B) -- a decrement landing at or below k is undone by an
+     *     atomic add; stats.atomics counts both. */
+    PICO_PO_STATIC = 0x800,
+    PICO_PO_ROLLBACK = 0x1000
 };
 
 /* Run statistics (all counts over the whole call). */
@@ -86,7 +99,8 @@ typedef struct pico_stats {
     int64_t frontier_total; /* PeelOne: vertices peeled (= non-isolated n);
                                HistoCore: sum over rounds of |V_cnt| */
     int32_t k_max;          /* largest coreness found (PeelOne; 0 for HistoCore) */
-    int32_t reserved;
+    int32_t algo_used;      /* the algorithm that ran (PICO_ALGO_PEELONE or
+                               PICO_ALGO_HISTOCORE), also under PICO_ALGO_AUTO */
     double elapsed_ms;      /* host wall time of the call's device work */
     int64_t edges_scanned;  /* adjacency entries read by the frontier kernels:
                                PeelOne scatter (= m), HistoCore UpdateHisto */
@@ -168,6 +182,32 @@ PICO_API int pico_coreness_update(const void *csr_offsets, const int32_t *csr_co
                                   int64_t m, int algo, const int32_t *prev_core, int32_t bound_add,
                                   int32_t *out_core, void *workspace, size_t ws_bytes,
                                   pico_stats *stats, void *stream);
+
+/*
+ * pico_select_algorithm -- the algorithm PICO_ALGO_AUTO runs on this graph
+ * (the hybrid the paper leaves to future work, Section VII; Table VII shows
+ * each paradigm ahead on different graphs).  Two features are measured on
+ * the device:
+ *   features[0]  H, the degree h-index: the largest h with at least h
+ *                vertices of degree >= h.  It bounds k_max, hence PeelOne's
+ *                level count (Table V: l1 = k_max).
+ *   features[1]  vertices sampled (1024 evenly spaced ids, those of degree 1
+ *                to 1024 counted),
+ *   features[2]  of those, the ones in HistoCore's first frontier, with
+ *                fewer than deg(v) neighbours of degree >= deg(v) (Theorem 2).
+ * Rule (constants from a sweep of 47 graphs on MI355X): m < 2^16 ->
+ * PeelOne; fewer than 1/64 of the sample in the first frontier -> HistoCore;
+ * m < 2^23 and H >= 4 m / n -> HistoCore; otherwise PeelOne.  For m < 2^16
+ * nothing is measured (features all 0).
+ *   algo         PICO_ALGO_AUTO, optionally | PICO_OFFSETS_I64.
+ *   workspace    at least pico_workspace_bytes(n, m, algo) bytes (device).
+ *   algo_out     host int: PICO_ALGO_PEELONE or PICO_ALGO_HISTOCORE.
+ *   features     host int64[3] or NULL.
+ * Synchronises `stream`.  Errors as pico_coreness_ws.
+ */
+PICO_API int pico_select_algorithm(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
+                                   int algo, void *workspace, size_t ws_bytes, int *algo_out,
+                                   int64_t *features, void *stream);
 
 /* Tuning of the batched kernel (NULL = defaults). */
 typedef struct pico_batch_tune {

@@ -10,6 +10,8 @@ Routines (each cites the passage of the paper it follows):
   plain definition of coreness from Section I.  Related work, Section VI-A.
 * ``hindex_jacobi``  -- the Index2core paradigm (Section II-A, Alg. 2) in
   synchronous rounds, h-index by sorting (C).
+* ``peel_static``    -- PeelOne without the dynamic frontier (the variant of
+  Table IV), serially, with its iteration count (C).
 * ``hindex_jacobi_from`` -- the same iteration started from upper bounds of
   the coreness (core maintenance after edge changes), never raising a value
   (C).
@@ -73,6 +75,9 @@ def _load():
         lib.oracle_hindex_jacobi.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
+        lib.oracle_peel_static.restype = ctypes.c_int64
+        lib.oracle_peel_static.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]
         lib.oracle_hindex_jacobi_from.restype = ctypes.c_int64
         lib.oracle_hindex_jacobi_from.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
@@ -125,6 +130,19 @@ def hindex_jacobi(offsets, cols, max_rounds: int = 1 << 30):
     if r < 0:
         raise RuntimeError(f"oracle_hindex_jacobi failed with {r}")
     return x, per_round[:r].tolist(), last
+
+
+def peel_static(offsets, cols):
+    """PeelOne without the dynamic frontier (Table IV's variant), serially:
+    returns (coreness, iterations), iterations counting every scan that found
+    a vertex at the current level (sub-iterations included)."""
+    off, adj = _csr_np(offsets, cols)
+    n = off.shape[0] - 1
+    x = np.zeros(max(n, 0), dtype=np.int32)
+    r = _load().oracle_peel_static(n, _ptr(off), _ptr(adj) if adj.size else None, _ptr(x))
+    if r < 0:
+        raise RuntimeError(f"oracle_peel_static failed with {r}")
+    return x, int(r)
 
 
 def hindex_jacobi_from(offsets, cols, x0, add: int = 0, max_rounds: int = 1 << 30):

@@ -16,6 +16,8 @@
  *                          Section I: core(v) = the largest k such that v lies
  *                          in the k-core, the maximal subgraph of minimum
  *                          degree >= k.
+ *  - oracle_peel_static:   PeelOne without the dynamic frontier (Table IV's
+ *                          variant), serially, counting its iterations.
  *  - oracle_hindex_jacobi_from: the same iteration started from upper bounds
  *                          of the coreness (core maintenance on a changed
  *                          graph), never raising a value.
@@ -224,4 +226,62 @@ int64_t oracle_hindex_jacobi_from(int64_t n, const int64_t *off, const int32_t *
     memcpy(x_out, x, sizeof(int32_t) * (size_t)n);
     free(x); free(y); free(buf);
     return rounds;
+}
+
+/*
+ * PeelOne without the dynamic frontier (the variant the paper measures in
+ * Table IV against Alg. 4's in-level frontier), executed serially: at level
+ * k each iteration takes the residual vertices whose residual degree equals
+ * k, removes them with coreness k, and decrements each residual neighbour
+ * whose residual degree is above k; vertices brought down to k wait for the
+ * next iteration at the same level.  A level ends when an iteration finds
+ * nobody; k then jumps to the smallest residual degree (an empty level is
+ * not an iteration).  Returns the number of iterations (Table IV's l1 for
+ * this variant), -1 on bad arguments, -2 on allocation failure; core_out
+ * gets the coreness.
+ */
+int64_t oracle_peel_static(int64_t n, const int64_t *off, const int32_t *adj, int32_t *core_out)
+{
+    if (n < 0 || (n > 0 && (!off || !core_out))) return -1;
+    if (n == 0) return 0;
+    int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    unsigned char *alive = (unsigned char *)malloc((size_t)n);
+    int32_t *frontier = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!deg || !alive || !frontier) { free(deg); free(alive); free(frontier); return -2; }
+    int64_t left = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        deg[v] = (int32_t)(off[v + 1] - off[v]);
+        alive[v] = deg[v] > 0;
+        core_out[v] = 0;
+        left += alive[v];
+    }
+    int64_t iterations = 0;
+    int32_t k = 1;
+    while (left > 0) {
+        int64_t nf = 0;
+        for (int64_t v = 0; v < n; ++v)
+            if (alive[v] && deg[v] == k) frontier[nf++] = (int32_t)v;
+        if (nf == 0) {  /* empty level: jump to the smallest residual degree */
+            int32_t mn = INT32_MAX;
+            for (int64_t v = 0; v < n; ++v)
+                if (alive[v] && deg[v] < mn) mn = deg[v];
+            k = mn;
+            continue;
+        }
+        ++iterations;
+        for (int64_t i = 0; i < nf; ++i) {
+            alive[frontier[i]] = 0;
+            core_out[frontier[i]] = k;
+        }
+        left -= nf;
+        for (int64_t i = 0; i < nf; ++i) {
+            int32_t v = frontier[i];
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                int32_t u = adj[e];
+                if (alive[u] && deg[u] > k) deg[u]--;
+            }
+        }
+    }
+    free(deg); free(alive); free(frontier);
+    return iterations;
 }

@@ -20,8 +20,10 @@ import torch  # loaded first so the library binds to the HIP runtime torch uses
 __all__ = [
     "PICO_OK", "PICO_EINVAL", "PICO_ENOMEM", "PICO_EHIP", "PICO_ENOTSUP", "PICO_EBADCSR",
     "PICO_ALGO_PEELONE", "PICO_ALGO_HISTOCORE", "PICO_OFFSETS_I64", "PICO_PATH_GRID", "PICO_PATH_WG",
+    "PICO_PO_STATIC", "PICO_PO_ROLLBACK", "VARIANTS",
     "PATHS", "PicoError", "PicoStats",
     "pico_coreness", "pico_coreness_ws", "pico_coreness_update", "coreness_update",
+    "pico_select_algorithm", "select_algorithm", "PICO_ALGO_AUTO", "SINGLE_ALGOS", "ALGO_NAMES",
     "pico_workspace_bytes", "pico_validate_csr",
     "pico_status_string", "pico_last_error", "pico_version", "coreness", "library_path",
     "load_library", "EXPORTED_SYMBOLS", "pico_profile_enable", "pico_profile_read",
@@ -33,12 +35,20 @@ __all__ = [
 ]
 
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
-PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE, PICO_OFFSETS_I64 = 0, 1, 0x100
+PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE, PICO_ALGO_AUTO, PICO_OFFSETS_I64 = 0, 1, 2, 0x100
 PICO_PATH_GRID, PICO_PATH_WG = 0x200, 0x400
+PICO_PO_STATIC, PICO_PO_ROLLBACK = 0x800, 0x1000
 PATHS = {None: 0, "auto": 0, "grid": PICO_PATH_GRID, "wg": PICO_PATH_WG}
 ALGOS = {"peelone": PICO_ALGO_PEELONE, "histocore": PICO_ALGO_HISTOCORE}
+# single-graph calls may also ask for the per-graph choice between the two
+SINGLE_ALGOS = {**ALGOS, "auto": PICO_ALGO_AUTO}
+ALGO_NAMES = {PICO_ALGO_PEELONE: "peelone", PICO_ALGO_HISTOCORE: "histocore"}
+# PeelOne ablations (single-graph calls): no dynamic frontier; rollback decrement
+VARIANTS = {"peelone-static": PICO_ALGO_PEELONE | PICO_PO_STATIC,
+            "peelone-rollback": PICO_ALGO_PEELONE | PICO_PO_ROLLBACK}
 
-EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update", "pico_workspace_bytes",
+EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update", "pico_select_algorithm",
+                    "pico_workspace_bytes",
                     "pico_validate_csr", "pico_status_string", "pico_last_error", "pico_version",
                     "pico_profile_enable", "pico_profile_read", "pico_batched_workspace_bytes",
                     "pico_coreness_batched", "pico_task_scratch_bytes",
@@ -60,13 +70,13 @@ class PicoError(RuntimeError):
 class PicoStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("sub_rounds", ctypes.c_int64),
                 ("scans", ctypes.c_int64), ("frontier_total", ctypes.c_int64),
-                ("k_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("k_max", ctypes.c_int32), ("algo_used", ctypes.c_int32),
                 ("elapsed_ms", ctypes.c_double), ("edges_scanned", ctypes.c_int64),
                 ("atomics", ctypes.c_int64), ("buckets_scanned", ctypes.c_int64),
                 ("pushes_dynamic", ctypes.c_int64), ("phase_ms", ctypes.c_double * 8)]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("reserved", "phase_ms")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "phase_ms"}
         d["phase_ms"] = [round(x, 4) for x in self.phase_ms]
         return d
 
@@ -162,6 +172,9 @@ def load_library():
     lib.pico_coreness_update.argtypes = [vp, vp, i64, i64, i32, vp, ctypes.c_int32, vp, vp,
                                          ctypes.c_size_t, ctypes.POINTER(PicoStats), vp]
     lib.pico_coreness_update.restype = i32
+    lib.pico_select_algorithm.argtypes = [vp, vp, i64, i64, i32, vp, ctypes.c_size_t, ctypes.POINTER(i32),
+                                          ctypes.POINTER(ctypes.c_int64), vp]
+    lib.pico_select_algorithm.restype = i32
     lib.pico_workspace_bytes.argtypes = [i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pico_workspace_bytes.restype = i32
     lib.pico_validate_csr.argtypes = [vp, vp, i64, i64, i32, vp]
@@ -360,7 +373,10 @@ def pico_validate_csr(csr_offsets, csr_cols, n: int, m: int, algo: int, stream=N
 def algo_code(algo, offsets: torch.Tensor, path=None) -> int:
     """The C algo word: algorithm, offset width and path ("grid", "wg" or
     None/"auto" for the library's choice by size)."""
-    a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    if isinstance(algo, str):
+        a = VARIANTS[algo] if algo in VARIANTS else SINGLE_ALGOS[algo]
+    else:
+        a = int(algo)
     a |= PATHS[path]
     if offsets.dtype == torch.int64:
         a |= PICO_OFFSETS_I64
@@ -397,6 +413,29 @@ def coreness(offsets: torch.Tensor, cols: torch.Tensor, algo="peelone", *, out=N
     _check(pico_coreness_ws(offsets, cols, n, m, a, out, workspace, workspace.numel(), st,
                             stream=stream))
     return (out, st.as_dict()) if with_stats else out
+
+
+def pico_select_algorithm(csr_offsets, csr_cols, n: int, m: int, algo: int, workspace, ws_bytes: int,
+                          stream=None):
+    """C ``pico_select_algorithm``: returns (status, chosen algo code, [H, sampled, in_frontier])."""
+    out = ctypes.c_int(0)
+    feat = (ctypes.c_int64 * 3)()
+    rc = load_library().pico_select_algorithm(_ptr(csr_offsets), _ptr(csr_cols), n, m, algo, _ptr(workspace),
+                                              ws_bytes, ctypes.byref(out), feat, _stream(stream))
+    return rc, out.value, list(feat)
+
+
+def select_algorithm(offsets: torch.Tensor, cols: torch.Tensor, workspace=None, stream=None):
+    """The algorithm PICO_ALGO_AUTO runs on this graph: (name, features
+    {"h_index", "sampled", "in_first_frontier"})."""
+    n = offsets.numel() - 1
+    m = cols.numel()
+    a = algo_code("auto", offsets)
+    if workspace is None:
+        workspace = workspace_for(n, m, a, offsets.device)
+    rc, chosen, f = pico_select_algorithm(offsets, cols, n, m, a, workspace, workspace.numel(), stream)
+    _check(rc)
+    return ALGO_NAMES[chosen], {"h_index": f[0], "sampled": f[1], "in_first_frontier": f[2]}
 
 
 def pico_coreness_update(csr_offsets, csr_cols, n: int, m: int, algo: int, prev_core, bound_add: int,

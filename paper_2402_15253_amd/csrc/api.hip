@@ -140,17 +140,28 @@ int prof_resolve() {
 int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo,
                const int32_t *out) {
     int a = algo & PICO_ALGO_MASK;
-    if (a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) {
+    if (a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) {
         set_error("unknown algo %d", algo);
         return PICO_EINVAL;
     }
-    if ((algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64 | PICO_PATH_GRID | PICO_PATH_WG)) != 0) {
+    if ((algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64 | PICO_PATH_GRID | PICO_PATH_WG | PICO_PO_STATIC |
+                  PICO_PO_ROLLBACK)) != 0) {
         set_error("unknown flag bits in algo 0x%x", algo);
         return PICO_EINVAL;
     }
     if ((algo & PICO_PATH_GRID) && (algo & PICO_PATH_WG)) {
         set_error("PICO_PATH_GRID and PICO_PATH_WG are exclusive");
         return PICO_EINVAL;
+    }
+    if (algo & (PICO_PO_STATIC | PICO_PO_ROLLBACK)) {
+        if (a != PICO_ALGO_PEELONE || ((algo & PICO_PO_STATIC) && (algo & PICO_PO_ROLLBACK))) {
+            set_error("PICO_PO_STATIC / PICO_PO_ROLLBACK: one of them, with PeelOne only");
+            return PICO_EINVAL;
+        }
+        if (algo & PICO_PATH_WG) {
+            set_error("the PeelOne ablations run on the grid path only");
+            return PICO_ENOTSUP;
+        }
     }
     if (n < 0 || m < 0) {
         set_error("negative size (n=%lld, m=%lld)", (long long)n, (long long)m);
@@ -178,10 +189,33 @@ int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int a
 
 // warm / warm_add: HistoCore started from given upper bounds (nullptr: from
 // the degrees).
+// The algorithm PICO_ALGO_AUTO runs on this graph (features measured only
+// when the rule needs them).
+int pick_algo(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo, void *ws,
+              size_t ws_bytes, hipStream_t s, int *chosen, int64_t feat[3]) {
+    feat[0] = feat[1] = feat[2] = 0;
+    *chosen = PICO_ALGO_PEELONE;
+    if (m < (1ll << 16)) return PICO_OK;  // the rule's first case needs no features
+    const bool i64 = (algo & PICO_OFFSETS_I64) != 0;
+    int rc = i64 ? select_features<int64_t>(static_cast<const int64_t *>(off), cols, n, m, ws, ws_bytes, s, feat)
+                 : select_features<int32_t>(static_cast<const int32_t *>(off), cols, n, m, ws, ws_bytes, s, feat);
+    if (rc) return rc;
+    *chosen = choose_algo(n, m, feat[0], feat[1], feat[2]);
+    return PICO_OK;
+}
+
 int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo, int32_t *out,
              void *ws, size_t ws_bytes, pico_stats *st, hipStream_t s, const int32_t *warm = nullptr,
              int warm_add = 0) {
     const bool i64 = (algo & PICO_OFFSETS_I64) != 0;
+    if ((algo & PICO_ALGO_MASK) == PICO_ALGO_AUTO) {
+        int chosen = PICO_ALGO_PEELONE;
+        int64_t feat[3];
+        int rc = pick_algo(off, cols, n, m, algo, ws, ws_bytes, s, &chosen, feat);
+        if (rc) return rc;
+        algo = (algo & ~PICO_ALGO_MASK) | chosen;
+    }
+    if (st) st->algo_used = algo & PICO_ALGO_MASK;
     bool small = false;
     int rc = small_path(n, m, algo, &small);
     if (rc) return rc;
@@ -191,10 +225,11 @@ int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int alg
                    : run_small<int32_t>(static_cast<const int32_t *>(off), cols, n, m, algo, out, ws,
                                         ws_bytes, st, s, warm, warm_add);
     if ((algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE) {
+        const int mode = (algo & PICO_PO_STATIC) ? 1 : (algo & PICO_PO_ROLLBACK) ? 2 : 0;
         return i64 ? run_peelone<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
-                                          ws_bytes, st, s)
+                                          ws_bytes, st, s, mode)
                    : run_peelone<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws,
-                                          ws_bytes, st, s);
+                                          ws_bytes, st, s, mode);
     }
     return i64 ? run_histocore<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
                                         ws_bytes, st, s, warm, warm_add)
@@ -225,9 +260,17 @@ __global__ void validate_kernel(const Off *__restrict__ off, const int32_t *__re
 }  // namespace
 
 size_t ws_bytes_for(int64_t n, int64_t m, int algo) {
+    const int a = algo & PICO_ALGO_MASK;
+    if (a == PICO_ALGO_AUTO) {  // either algorithm, and the features before it
+        size_t b = select_ws_bytes(n, m);
+        for (int x : {PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE}) {
+            const size_t w = ws_bytes_for(n, m, (algo & ~PICO_ALGO_MASK) | x);
+            if (w > b) b = w;
+        }
+        return b;
+    }
     // enough for either path, so the path may change without a new workspace
-    const size_t grid = (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m)
-                                                                      : histocore_ws_bytes(n, m);
+    const size_t grid = a == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m) : histocore_ws_bytes(n, m);
     const size_t small = small_ws_bytes(n, m, algo);
     return grid > small ? grid : small;
 }
@@ -373,6 +416,39 @@ int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n
     clear_error();
     return coreness_ws(csr_offsets, csr_cols, n, m, algo, out_core, workspace, ws_bytes, stats, stream,
                        nullptr, 0);
+}
+
+int pico_select_algorithm(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,
+                          void *workspace, size_t ws_bytes, int *algo_out, int64_t *features, void *stream) {
+    clear_error();
+    if ((algo & PICO_ALGO_MASK) != PICO_ALGO_AUTO || (algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64)) != 0) {
+        set_error("pico_select_algorithm takes PICO_ALGO_AUTO (| PICO_OFFSETS_I64), got 0x%x", algo);
+        return PICO_EINVAL;
+    }
+    if (!algo_out) {
+        set_error("NULL algo_out");
+        return PICO_EINVAL;
+    }
+    int32_t dummy_out = 0;
+    int rc = check_args(csr_offsets, csr_cols, n, m, algo, &dummy_out);
+    if (rc) return rc;
+    int64_t feat[3] = {0, 0, 0};
+    *algo_out = PICO_ALGO_PEELONE;
+    if (n > 0) {
+        rc = check_device();
+        if (rc) return rc;
+        const size_t need = ws_bytes_for(n, m, algo);
+        if (ws_bytes < need || !workspace) {
+            set_error("workspace of %zu bytes given, %zu needed", ws_bytes, need);
+            return PICO_ENOMEM;
+        }
+        rc = pick_algo(csr_offsets, csr_cols, n, m, algo, workspace, ws_bytes, static_cast<hipStream_t>(stream),
+                       algo_out, feat);
+        if (rc) return rc;
+    }
+    if (features)
+        for (int i = 0; i < 3; ++i) features[i] = feat[i];
+    return PICO_OK;
 }
 
 int pico_coreness_update(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,

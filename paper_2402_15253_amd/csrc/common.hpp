@@ -577,11 +577,22 @@ void prof_end(int rec, hipStream_t s);
 size_t peelone_ws_bytes(int64_t n, int64_t m);
 size_t histocore_ws_bytes(int64_t n, int64_t m);
 
+// mode: 0 = Alg. 4 (assertion, dynamic frontier); 1 = no dynamic frontier;
+// 2 = fetch-and-add rollback decrement (the paper's comparison variants).
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
-                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream);
+                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream, int mode = 0);
 
 size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo);
+
+// Choice between PeelOne and HistoCore (PICO_ALGO_AUTO): features measured on
+// the device -- feat[0] the degree h-index, feat[1] vertices sampled,
+// feat[2] of those in HistoCore's first frontier -- and the rule over them.
+size_t select_ws_bytes(int64_t n, int64_t m);
+template <typename Off>
+int select_features(const Off *off, const int32_t *cols, int64_t n, int64_t m, void *ws, size_t ws_bytes,
+                    hipStream_t stream, int64_t feat[3]);
+int choose_algo(int64_t n, int64_t m, int64_t H, int64_t sampled, int64_t in_frontier);
 
 // One graph by one workgroup, vertex values in LDS (graphs small enough that
 // grid barriers would dominate).  small_path decides from n, m and the path

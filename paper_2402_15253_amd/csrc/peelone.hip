@@ -61,6 +61,18 @@ constexpr int kLq = 2048;          // LDS continuation queue per workgroup
 constexpr int kLocalMax = 4096;    // an LDS batch is expanded locally up to this many edges
 constexpr int kTile = kBlock * 8;  // scan items per block step
 
+// Ablations of Alg. 4 (the variants the paper measures against):
+//   kStatic   -- no dynamic frontier (Table IV): a decrement never claims;
+//                vertices brought down to k wait for the next scan at the same
+//                level, which takes every survivor at or below k.  Scanned
+//                vertices always go to the global list, so no decrement of an
+//                iteration overlaps its scan and the iteration count is the
+//                serial one.
+//   kRollback -- the decrement of PP-dyn style methods (Section III-B): a
+//                fetch-and-subtract that lands at or below k is undone with a
+//                fetch-and-add, each counted as an atomic.
+enum { kDynamic = 0, kStatic = 1, kRollback = 2 };
+
 // Cumulative counters of the grid state.  QET packs (edges << 31) | slots of
 // the global frontier list.
 enum { QET = 0, N_DYN, N_ATOM };
@@ -91,6 +103,7 @@ struct PoArgs {
     unsigned long long limit;  // wall-clock ticks any single wait may last
     long long *trace;          // optional per-level record (development aid), or null
     int trace_cap;
+    int mode;                  // kDynamic, or an ablation: kStatic, kRollback
 };
 
 __global__ void po_state_init(PoState *st) {
@@ -124,6 +137,7 @@ struct PoCtx {
     int k;
     int natom;
     int ndyn;
+    int mode;
 };
 
 // Append the lanes' vertices to the global frontier list (one atomic per
@@ -203,6 +217,16 @@ __device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kE
         if (act[r] && cu[r] > c.k) {
             old[r] = atomicSub(&c.core[u[r]], 1);
             ++c.natom;
+        }
+    }
+    if (c.mode == kStatic) return;  // lowered vertices wait for the next scan
+    if (c.mode == kRollback) {
+#pragma unroll
+        for (int r = 0; r < kEbR; ++r) {
+            if (act[r] && cu[r] > c.k && old[r] <= c.k) {
+                atomicAdd(&c.core[u[r]], 1);
+                ++c.natom;
+            }
         }
     }
     bool push[kEbR];
@@ -320,7 +344,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
                 sv |= 1u << r;
                 lmin = min(lmin, cv);
             }
-            if (cv == k) cand |= 1u << r;
+            if (cv == k || (c.mode == kStatic && v >= 0 && cv < k)) cand |= 1u << r;
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -343,7 +367,8 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
         if (tf == 0) continue;
         claimed += tf;
         const unsigned tail = *c.lq.tail, keep = *c.lq.keep;
-        const bool local = local_edges + te <= kLocalMax && tail + tf - keep <= (unsigned)kLq;
+        const bool local = c.mode != kStatic && local_edges + te <= kLocalMax &&
+                           tail + tf - keep <= (unsigned)kLq;
         if (local) {
             local_edges += te;
 #pragma unroll
@@ -411,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     unsigned long long bar = 0;
     if (threadIdx.x == 0) lq_take = lq_tail = lq_keep = 0;
     PoCtx<Off> c{a.off, a.core, a.out, a.Q, a.QE, a.QR, &gs->ctr[QET].v,
-                 LdsQueue{lq_buf, &lq_take, &lq_tail, &lq_keep}, 0, 0, 0};
+                 LdsQueue{lq_buf, &lq_take, &lq_tail, &lq_keep}, 0, 0, 0, a.mode};
 
     const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
     PhaseClock clk;
@@ -477,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
         ++levels;
         kmax = c.k;
         if (nprev == 0) break;  // no survivor left after this level's scan: all claimed
-        c.k += 1;
+        if (a.mode != kStatic) c.k += 1;  // static: rescan the same level
     }
     long long t = wave_sum64(c.natom);
     if (lane_id() == 0 && t) atomicAdd(&gs->ctr[N_ATOM].v, (unsigned long long)t);
@@ -500,7 +525,7 @@ size_t peelone_ws_bytes(int64_t n, int64_t m) {
 
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
-                size_t ws_bytes, pico_stats *stats, hipStream_t stream) {
+                size_t ws_bytes, pico_stats *stats, hipStream_t stream, int mode) {
     if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
         set_error("m=%lld too large for the packed frontier counter", (long long)m);
         return PICO_ENOTSUP;
@@ -526,6 +551,7 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     a.limit = wall_ticks(20.0);
     a.trace = nullptr;
     a.trace_cap = 0;
+    a.mode = mode;
     const char *trace_file = getenv("PICO_TRACE_FILE");  // development aid
     if (trace_file && *trace_file) {
         a.trace_cap = 1 << 14;
@@ -592,8 +618,8 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
 }
 
 template int run_peelone<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                  void *, size_t, pico_stats *, hipStream_t);
+                                  void *, size_t, pico_stats *, hipStream_t, int);
 template int run_peelone<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                  void *, size_t, pico_stats *, hipStream_t);
+                                  void *, size_t, pico_stats *, hipStream_t, int);
 
 }  // namespace pico

@@ -106,7 +106,7 @@ def traffic(dir_fetch: str, dir_write: str) -> dict:
     return out
 
 
-_LINE = re.compile(r"^traffic (\w+) (\w+) bytes_per_launch=(\d+) source=([0-9a-f]+)\s*$")
+_LINE = re.compile(r"^traffic (\w+) ([\w-]+) bytes_per_launch=(\d+) source=([0-9a-f]+)\s*$")
 
 
 def format_traffic(t: dict, config: str) -> str:

@@ -5,6 +5,7 @@ import os
 import re
 
 import pytest
+import torch
 
 import paper_2402_15253_amd as pico
 
@@ -57,7 +58,23 @@ def test_argument_errors_need_no_device():
     assert pico.pico_coreness(None, None, 0, 0, both, None) == pico.PICO_EINVAL
     assert "exclusive" in pico.pico_last_error()
     assert pico.pico_coreness(None, None, 0, 0, pico.PICO_PATH_WG, None) == pico.PICO_OK
-    assert pico.pico_coreness(None, None, 0, 0, 0x800, None) == pico.PICO_EINVAL
+    assert pico.pico_coreness(None, None, 0, 0, 0x4000, None) == pico.PICO_EINVAL
+    # PeelOne ablations: one at a time, PeelOne only, grid path only
+    po, hc_ = pico.PICO_ALGO_PEELONE, pico.PICO_ALGO_HISTOCORE
+    st_, rb = pico.PICO_PO_STATIC, pico.PICO_PO_ROLLBACK
+    assert pico.pico_coreness(None, None, 0, 0, po | st_ | rb, None) == pico.PICO_EINVAL
+    assert pico.pico_coreness(None, None, 0, 0, hc_ | st_, None) == pico.PICO_EINVAL
+    assert pico.pico_coreness(None, None, 0, 0, po | rb | pico.PICO_PATH_WG, None) == pico.PICO_ENOTSUP
+    assert pico.pico_coreness(None, None, 0, 0, po | st_, None) == pico.PICO_OK
+    assert pico.algo_code("peelone-static", torch.zeros(1, dtype=torch.int64)) == (
+        po | st_ | pico.PICO_OFFSETS_I64)
+    # algorithm choice: PICO_ALGO_AUTO only; n == 0 picks PeelOne without device work
+    rc, chosen, feat = pico.pico_select_algorithm(None, None, 0, 0, pico.PICO_ALGO_AUTO, None, 0)
+    assert (rc, chosen, feat) == (pico.PICO_OK, pico.PICO_ALGO_PEELONE, [0, 0, 0])
+    assert pico.pico_select_algorithm(None, None, 0, 0, pico.PICO_ALGO_PEELONE, None, 0)[0] == pico.PICO_EINVAL
+    assert pico.pico_coreness(None, None, 0, 0, pico.PICO_ALGO_AUTO, None) == pico.PICO_OK
+    assert pico.pico_workspace_bytes(1000, 8000, pico.PICO_ALGO_AUTO) >= max(
+        pico.pico_workspace_bytes(1000, 8000, a) for a in (pico.PICO_ALGO_PEELONE, pico.PICO_ALGO_HISTOCORE))
     # core maintenance: HistoCore only, bounds required, bound_add >= 0
     up = pico.pico_coreness_update
     hc = pico.PICO_ALGO_HISTOCORE

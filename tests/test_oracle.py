@@ -350,3 +350,43 @@ def test_start_below_coreness_is_not_repaired():
     g = gg.complete(8)  # coreness 7 everywhere
     x, pr, _ = oracle.hindex_jacobi_from(g.offsets, g.cols, np.full(8, 3, dtype=np.int32))
     assert (x == 3).all() and pr == []
+
+
+# ---------------------------------------------------------------- PeelOne without the dynamic frontier
+# (the variant of Table IV): same coreness, more iterations.  Pins: closed
+# forms for paths, cycles, cliques and stars, and G1's narrative (Section
+# III-C, Fig. 5: at k = 2 the scan finds v2, v4 and v3, v5 only reach 2 during
+# the level, so without the dynamic frontier they need a second iteration).
+
+def test_static_peel_g1(golden_g1):
+    g = gg.g1()
+    x, it = oracle.peel_static(g.offsets, g.cols)
+    assert x.tolist() == [int(c) for c in golden_g1["coreness"]]
+    levels = len(set(int(c) for c in golden_g1["coreness"] if int(c) > 0))
+    assert golden_g1["peelone_k2_dynamic"]  # vertices that wait for a second iteration
+    assert it == levels + 1 == 3
+
+
+@pytest.mark.parametrize("n", [2, 3, 10, 51, 200])
+def test_static_peel_path_closed_form(n):
+    g = gg.path(n)
+    x, it = oracle.peel_static(g.offsets, g.cols)
+    assert (x == 1).all()
+    assert it == (n + 1) // 2  # the two ends go each iteration
+
+
+def test_static_peel_closed_forms():
+    for g, iters in ((gg.cycle(40), 1), (gg.complete(30), 1), (gg.star(25), 2), (gg.hypercube(5), 1),
+                     (gg.empty_graph(4), 0)):
+        x, it = oracle.peel_static(g.offsets, g.cols)
+        assert np.array_equal(x, oracle.bz_coreness(g.offsets, g.cols)), g.name
+        assert it == iters, g.name
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_static_peel_matches_bz_and_needs_more_iterations(seed):
+    g = gg.rmat(11, 8, 60 + seed) if seed % 2 else gg.er_gnp(2000, 6.0, 60 + seed)
+    want = oracle.bz_coreness(g.offsets, g.cols)
+    x, it = oracle.peel_static(g.offsets, g.cols)
+    assert np.array_equal(x, want)
+    assert it >= len(np.unique(want[want > 0]))
