@@ -689,6 +689,27 @@ def main():
             ablations[variant] = {"ms": round(min(times), 3), "iterations": vst.iterations,
                                   "atomics": vst.atomics, "pushes_dynamic": vst.pushes_dynamic,
                                   "identical": bool(torch.equal(vout, outs["peelone"]))}
+        # Index2core baselines against HistoCore (Table VIII): same rounds,
+        # every h-index rebuilt from the neighbours
+        i2c_bytes = max(pico.pico_workspace_bytes(n, m, pico.algo_code(v, g.offsets))
+                        for v in ("cntcore", "nbrcore"))
+        i2c_ws = torch.empty(max(i2c_bytes, ws_bytes), dtype=torch.uint8, device=dev)
+        for variant in ("histocore", "cntcore", "nbrcore"):
+            code = pico.algo_code(variant, g.offsets)
+            vout = torch.empty(n, dtype=torch.int32, device=dev)
+            vst = pico.PicoStats()
+            times = []
+            for _ in range(2):
+                rc = pico.pico_coreness_ws(g.offsets, g.cols, n, m, code, vout, i2c_ws, i2c_ws.numel(), vst,
+                                           stream)
+                if rc != pico.PICO_OK:
+                    raise pico.PicoError(rc, pico.pico_last_error())
+                times.append(vst.elapsed_ms)
+            ablations[variant] = {"ms": round(min(times), 3), "iterations": vst.iterations,
+                                  "hindex_computed": vst.frontier_total, "edges_scanned": vst.edges_scanned,
+                                  "atomics": vst.atomics,
+                                  "identical": bool(torch.equal(vout, outs["peelone"]))}
+        del i2c_ws
         log(f"ablations: {ablations}")
 
     if args.copy_calibration:

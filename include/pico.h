@@ -63,6 +63,20 @@ enum {
     PICO_ALGO_HISTOCORE = 1,
     PICO_ALGO_AUTO = 2,       /* single-graph calls: PeelOne or HistoCore, chosen per
                                  graph by pico_select_algorithm's rule */
+    /* Index2core baselines HistoCore is measured against (Section IV-A,
+     * Alg. 5; Section V, Table VIII), single-graph calls on the grid path:
+     * synchronous rounds from the degrees with every h-index rebuilt from
+     * the neighbours' values.  CntCore recomputes only vertices whose cnt
+     * (neighbours valued >= their own value) fell below their value
+     * (Theorem 2); NbrCore recomputes every neighbour of a vertex that
+     * changed.  Same coreness.  Their pico_stats: iterations = rounds that
+     * changed a value (l2), sub_rounds = rounds that computed h-indexes,
+     * scans = active vertices (cnt computed / recompute candidates) summed
+     * over rounds, frontier_total = h-indexes computed, edges_scanned = all
+     * adjacency entries read, atomics = histogram and cnt increments,
+     * pushes_dynamic = activations after the first round. */
+    PICO_ALGO_CNTCORE = 3,
+    PICO_ALGO_NBRCORE = 4,
     PICO_ALGO_MASK = 0xff,
     PICO_OFFSETS_I64 = 0x100, /* OR-ed into algo: csr_offsets is int64[n+1] */
     /* Path selection, OR-ed into algo (single-graph calls only; at most one).

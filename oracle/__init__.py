@@ -10,6 +10,9 @@ Routines (each cites the passage of the paper it follows):
   plain definition of coreness from Section I.  Related work, Section VI-A.
 * ``hindex_jacobi``  -- the Index2core paradigm (Section II-A, Alg. 2) in
   synchronous rounds, h-index by sorting (C).
+* ``index2core``     -- CntCore (Section IV-A, Alg. 5) and NbrCore (the
+  Index2core baseline of Section V) in synchronous rounds, with work counts
+  (C).
 * ``peel_static``    -- PeelOne without the dynamic frontier (the variant of
   Table IV), serially, with its iteration count (C).
 * ``hindex_jacobi_from`` -- the same iteration started from upper bounds of
@@ -75,6 +78,9 @@ def _load():
         lib.oracle_hindex_jacobi.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
+        lib.oracle_index2core.restype = ctypes.c_int
+        lib.oracle_index2core.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_peel_static.restype = ctypes.c_int64
         lib.oracle_peel_static.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]
@@ -130,6 +136,26 @@ def hindex_jacobi(offsets, cols, max_rounds: int = 1 << 30):
     if r < 0:
         raise RuntimeError(f"oracle_hindex_jacobi failed with {r}")
     return x, per_round[:r].tolist(), last
+
+
+INDEX2CORE_COUNTS = ("rounds_changed", "rounds_run", "active", "hindex_computed", "edges_cnt",
+                     "edges_hindex", "edges_mark", "activations")
+
+
+def index2core(offsets, cols, variant: str):
+    """CntCore (Alg. 5) or NbrCore in synchronous rounds from the degrees,
+    every h-index recomputed from the neighbours' values (no maintained
+    histogram).  Returns (coreness, {count name: value}) with the counts of
+    INDEX2CORE_COUNTS."""
+    mode = {"nbrcore": 0, "cntcore": 1}[variant]
+    off, adj = _csr_np(offsets, cols)
+    n = off.shape[0] - 1
+    x = np.zeros(max(n, 0), dtype=np.int32)
+    out = np.zeros(8, dtype=np.int64)
+    r = _load().oracle_index2core(n, _ptr(off), _ptr(adj) if adj.size else None, mode, _ptr(x), _ptr(out))
+    if r < 0:
+        raise RuntimeError(f"oracle_index2core failed with {r}")
+    return x, dict(zip(INDEX2CORE_COUNTS, (int(v) for v in out)))
 
 
 def peel_static(offsets, cols):

@@ -16,6 +16,8 @@
  *                          Section I: core(v) = the largest k such that v lies
  *                          in the k-core, the maximal subgraph of minimum
  *                          degree >= k.
+ *  - oracle_index2core:    CntCore (Alg. 5) and NbrCore, synchronous rounds,
+ *                          with their work counts (Table VIII's baselines).
  *  - oracle_peel_static:   PeelOne without the dynamic frontier (Table IV's
  *                          variant), serially, counting its iterations.
  *  - oracle_hindex_jacobi_from: the same iteration started from upper bounds
@@ -284,4 +286,105 @@ int64_t oracle_peel_static(int64_t n, const int64_t *off, const int32_t *adj, in
     }
     free(deg); free(alive); free(frontier);
     return iterations;
+}
+
+/*
+ * CntCore (Alg. 5) and NbrCore (the Index2core baseline the paper compares
+ * with, Section V: a vertex whose value changed makes all its neighbours
+ * recompute), in synchronous rounds from x = deg, the h-index recomputed
+ * from scratch for every vertex that needs it (no maintained histogram).
+ *   CntCore (mode 1): round t takes the active set A (all vertices in round
+ *     1, afterwards the neighbours of the previous frontier), computes
+ *     cnt(v) = |{u in nbr(v) : x(u) >= x(v)}| for v in A, and the frontier
+ *     F = {v in A : cnt(v) < x(v)} (Theorem 2: exactly the vertices whose
+ *     h-index drops); if F is empty it stops; each v in F takes the h-index
+ *     of its neighbours' values; the next A is the union of F's neighbours.
+ *   NbrCore (mode 0): every v in A takes the h-index of its neighbours'
+ *     values (capped at x(v)); C = those that changed; if C is empty it stops;
+ *     the next A is the union of C's neighbours.
+ * out[0] rounds that changed a value, [1] rounds run, [2] sum |A|, [3] sum of
+ * h-index computations (|F| or |A|), [4] adjacency entries read by cnt
+ * scans, [5] by h-index computations, [6] by neighbour marking, [7] sum over
+ * rounds of activations after round 1.  x_out gets the coreness.  Returns 0,
+ * -1 on bad arguments, -2 on allocation failure.
+ */
+int oracle_index2core(int64_t n, const int64_t *off, const int32_t *adj, int mode, int32_t *x_out,
+                      int64_t *out)
+{
+    if (n < 0 || (n > 0 && (!off || !x_out)) || !out || (mode != 0 && mode != 1)) return -1;
+    for (int i = 0; i < 8; ++i) out[i] = 0;
+    if (n == 0) return 0;
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (off[v + 1] - off[v] > maxdeg) maxdeg = off[v + 1] - off[v];
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *y = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *act = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *nxt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *fr = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+    if (!x || !y || !act || !nxt || !fr || !mark || !buf) {
+        free(x); free(y); free(act); free(nxt); free(fr); free(mark); free(buf);
+        return -2;
+    }
+    int64_t na = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        x[v] = (int32_t)(off[v + 1] - off[v]);
+        mark[v] = 0;
+        if (x[v] > 0) act[na++] = (int32_t)v;
+    }
+    for (int64_t t = 1; na > 0; ++t) {
+        out[1] += 1;
+        out[2] += na;
+        int64_t nf = 0;
+        if (mode == 1) {
+            for (int64_t i = 0; i < na; ++i) {
+                int32_t v = act[i];
+                int64_t cnt = 0;
+                for (int64_t e = off[v]; e < off[v + 1]; ++e) cnt += x[adj[e]] >= x[v];
+                out[4] += off[v + 1] - off[v];
+                if (cnt < x[v]) fr[nf++] = v;
+            }
+            if (nf == 0) { out[1] -= 1; break; }  /* an empty frontier ends the run before any h-index */
+        } else {
+            for (int64_t i = 0; i < na; ++i) fr[nf++] = act[i];
+        }
+        out[3] += nf;
+        /* h-index from the previous round's values for every frontier vertex */
+        int64_t nc = 0;
+        for (int64_t i = 0; i < nf; ++i) {
+            int32_t v = fr[i];
+            int64_t d = off[v + 1] - off[v];
+            for (int64_t j = 0; j < d; ++j) buf[j] = x[adj[off[v] + j]];
+            out[5] += d;
+            int32_t h = h_index_sorted(buf, d);
+            y[v] = h < x[v] ? h : x[v];
+        }
+        for (int64_t i = 0; i < nf; ++i) {
+            int32_t v = fr[i];
+            if (y[v] != x[v]) fr[nc++] = v;
+        }
+        for (int64_t i = 0; i < nc; ++i) x[fr[i]] = y[fr[i]];
+        if (nc == 0) break;
+        out[0] += 1;
+        int64_t nn = 0;
+        for (int64_t i = 0; i < nc; ++i) {
+            int32_t v = fr[i];
+            out[6] += off[v + 1] - off[v];
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                int32_t u = adj[e];
+                if (mark[u] != t) {
+                    mark[u] = t;
+                    nxt[nn++] = u;
+                }
+            }
+        }
+        out[7] += nn;
+        int32_t *tmp = act; act = nxt; nxt = tmp;
+        na = nn;
+    }
+    memcpy(x_out, x, sizeof(int32_t) * (size_t)n);
+    free(x); free(y); free(act); free(nxt); free(fr); free(mark); free(buf);
+    return 0;
 }

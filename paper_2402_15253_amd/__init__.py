@@ -20,7 +20,7 @@ import torch  # loaded first so the library binds to the HIP runtime torch uses
 __all__ = [
     "PICO_OK", "PICO_EINVAL", "PICO_ENOMEM", "PICO_EHIP", "PICO_ENOTSUP", "PICO_EBADCSR",
     "PICO_ALGO_PEELONE", "PICO_ALGO_HISTOCORE", "PICO_OFFSETS_I64", "PICO_PATH_GRID", "PICO_PATH_WG",
-    "PICO_PO_STATIC", "PICO_PO_ROLLBACK", "VARIANTS",
+    "PICO_PO_STATIC", "PICO_PO_ROLLBACK", "VARIANTS", "PICO_ALGO_CNTCORE", "PICO_ALGO_NBRCORE",
     "PATHS", "PicoError", "PicoStats",
     "pico_coreness", "pico_coreness_ws", "pico_coreness_update", "coreness_update",
     "pico_select_algorithm", "select_algorithm", "PICO_ALGO_AUTO", "SINGLE_ALGOS", "ALGO_NAMES",
@@ -44,8 +44,11 @@ ALGOS = {"peelone": PICO_ALGO_PEELONE, "histocore": PICO_ALGO_HISTOCORE}
 SINGLE_ALGOS = {**ALGOS, "auto": PICO_ALGO_AUTO}
 ALGO_NAMES = {PICO_ALGO_PEELONE: "peelone", PICO_ALGO_HISTOCORE: "histocore"}
 # PeelOne ablations (single-graph calls): no dynamic frontier; rollback decrement
+PICO_ALGO_CNTCORE, PICO_ALGO_NBRCORE = 3, 4
 VARIANTS = {"peelone-static": PICO_ALGO_PEELONE | PICO_PO_STATIC,
-            "peelone-rollback": PICO_ALGO_PEELONE | PICO_PO_ROLLBACK}
+            "peelone-rollback": PICO_ALGO_PEELONE | PICO_PO_ROLLBACK,
+            # Index2core baselines (Table VIII): every h-index rebuilt from the neighbours
+            "cntcore": PICO_ALGO_CNTCORE, "nbrcore": PICO_ALGO_NBRCORE}
 
 EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update", "pico_select_algorithm",
                     "pico_workspace_bytes",

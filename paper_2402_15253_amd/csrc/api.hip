@@ -140,9 +140,14 @@ int prof_resolve() {
 int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo,
                const int32_t *out) {
     int a = algo & PICO_ALGO_MASK;
-    if (a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) {
+    if (a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO && a != PICO_ALGO_CNTCORE &&
+        a != PICO_ALGO_NBRCORE) {
         set_error("unknown algo %d", algo);
         return PICO_EINVAL;
+    }
+    if ((a == PICO_ALGO_CNTCORE || a == PICO_ALGO_NBRCORE) && (algo & PICO_PATH_WG)) {
+        set_error("CntCore and NbrCore run on the grid path only");
+        return PICO_ENOTSUP;
     }
     if ((algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64 | PICO_PATH_GRID | PICO_PATH_WG | PICO_PO_STATIC |
                   PICO_PO_ROLLBACK)) != 0) {
@@ -216,6 +221,14 @@ int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int alg
         algo = (algo & ~PICO_ALGO_MASK) | chosen;
     }
     if (st) st->algo_used = algo & PICO_ALGO_MASK;
+    const int base = algo & PICO_ALGO_MASK;
+    if (base == PICO_ALGO_CNTCORE || base == PICO_ALGO_NBRCORE) {
+        const int mode = base == PICO_ALGO_CNTCORE ? 1 : 0;
+        return i64 ? run_index2core<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws, ws_bytes, st,
+                                             s, mode)
+                   : run_index2core<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws, ws_bytes, st,
+                                             s, mode);
+    }
     bool small = false;
     int rc = small_path(n, m, algo, &small);
     if (rc) return rc;
@@ -269,6 +282,7 @@ size_t ws_bytes_for(int64_t n, int64_t m, int algo) {
         }
         return b;
     }
+    if (a == PICO_ALGO_CNTCORE || a == PICO_ALGO_NBRCORE) return index2core_ws_bytes(n, m);
     // enough for either path, so the path may change without a new workspace
     const size_t grid = a == PICO_ALGO_PEELONE ? peelone_ws_bytes(n, m) : histocore_ws_bytes(n, m);
     const size_t small = small_ws_bytes(n, m, algo);

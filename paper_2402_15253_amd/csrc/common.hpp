@@ -622,6 +622,13 @@ int run_batched(const long long *vptr, const long long *off, const int32_t *cols
                 void *ws, size_t ws_bytes, const pico_batch_tune *tune, pico_batch_stats *stats,
                 hipStream_t stream);
 
+// CntCore (cnt_mode 1) or NbrCore (0): Index2core with every h-index rebuilt
+// from the neighbours' values, the baselines of the paper's Table VIII.
+size_t index2core_ws_bytes(int64_t n, int64_t m);
+template <typename Off>
+int run_index2core(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
+                   size_t ws_bytes, pico_stats *stats, hipStream_t stream, int cnt_mode);
+
 // warm (optional): start from these upper bounds of the coreness, plus
 // warm_add, instead of the degrees.
 template <typename Off>

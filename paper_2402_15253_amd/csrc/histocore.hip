@@ -514,6 +514,191 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
     }
 }
 
+
+// ---------------------------------------------------------------- CntCore / NbrCore
+//
+// The Index2core baselines the paper measures HistoCore against (Section
+// IV-A, Alg. 5, and Section V, Table VIII), in synchronous rounds from the
+// degrees, with every h-index rebuilt from the neighbours' values (Step I
+// and Step II of Fig. 6 each time; no histogram carried between rounds):
+//   CntCore -- round t counts, for each vertex of the active set A (all
+//     vertices in the first round, afterwards the neighbours of the previous
+//     frontier), cnt(v) = |{u in nbr(v) : core[u] >= core[v]}|; the frontier
+//     is {v in A : cnt(v) < core[v]} (Theorem 2), and only it recomputes.
+//   NbrCore -- every vertex of A recomputes; A is then the neighbours of the
+//     vertices whose value changed.
+// Per round: [cnt scan] -> frontier (+ clear its histogram rows) -> Step I
+// -> Step II (SumHisto, shared with HistoCore) -> mark the neighbours of the
+// changed vertices into the next active list.  All passes over adjacency are
+// edge-balanced.
+
+// Counter slots: the frontier list (FET) and heavy sums (HS_TAIL) and the
+// bucket count (N_BUCKETS) keep HistoCore's positions, which SumHisto uses.
+enum { IC_AET = H_TAIL, IC_ATOM = N_MOVES, IC_EDGES = N_EDGES };
+
+template <typename Off>
+struct IcArgs {
+    HcArgs<Off> h;     // core (the output), histo, oldcore, frontier lists F[0]/FE[0]/FR[0], P0, P1, HS, st
+    int32_t *cnt;      // per vertex
+    int32_t *mark;     // per vertex: the round that last put it in the next active list
+    int32_t *A[2];     // active lists, by round parity
+    long long *AE[2];  // ... row start in the list's concatenated edge space
+    long long *AR[2];  // ... first CSR position of the row
+    int cnt_mode;      // 1: CntCore, 0: NbrCore
+};
+
+template <typename Off>
+__global__ __launch_bounds__(kBlock) void ic_persistent(IcArgs<Off> a) {
+    __shared__ int part[kBlock];
+    __shared__ int first_ok;
+    __shared__ unsigned long long snap[kNumCtr + 1];
+    __shared__ EbLds eb;
+    const HcArgs<Off> &h = a.h;
+    HcState *st = h.st;
+    GridState *gs = &st->g;
+    const unsigned nb = gridDim.x;
+    unsigned long long bar = 0;
+    long long natom = 0, nbuck = 0, nedge = 0;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+
+    // core = deg; every vertex with neighbours is active in the first round
+    for (long long base = (long long)blockIdx.x * kBlock; base < h.n; base += (long long)gridDim.x * kBlock) {
+        const long long v = base + threadIdx.x;
+        int d = 0;
+        long long rs = 0;
+        if (v < h.n) {
+            rs = (long long)h.off[v];
+            d = (int)((long long)h.off[v + 1] - rs);
+            h.core[v] = d;
+            a.cnt[v] = 0;
+            a.mark[v] = 0;
+        }
+        wave_push_packed(v < h.n && d > 0, (int)v, rs, d, &gs->ctr[IC_AET].v, 0, a.A[0], a.AE[0], a.AR[0]);
+    }
+    if (!grid_sync<kSnap>(gs, nb, h.limit, snap, bar)) return;
+    long long na = (long long)(snap[IC_AET] & kSlotMask);
+    long long ea = (long long)(snap[IC_AET] >> kSlotBits);
+    long long rounds_changed = 0, rounds_run = 0, active = 0, hidx = 0, activations = 0;
+    for (int t = 1; na > 0; ++t) {
+        const int cur = (t - 1) & 1, nxt = cur ^ 1;
+        active += na;
+        if (lead) {
+            atomicExch(&gs->ctr[FET].v, 0ull);
+            atomicExch(&gs->ctr[IC_AET].v, 0ull);  // the next list fills in the marking pass
+        }
+        if (a.cnt_mode) {  // cnt of every active vertex
+            nedge += lead ? ea : 0;
+            edge_balanced(a.A[cur], a.AE[cur], a.AR[cur], nullptr, nullptr, 0, na, 0ll, ea, h.cols, nullptr, eb,
+                          [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR], EbLds &L,
+                              const int (&)[kEbR]) {
+#pragma unroll
+                              for (int r = 0; r < kEbR; ++r) {
+                                  if (!act[r]) continue;
+                                  const int v = L.id[own[r]];
+                                  if (h.core[u[r]] >= h.core[v]) {
+                                      atomicAdd(&a.cnt[v], 1);
+                                      ++natom;
+                                  }
+                              }
+                          });
+        }
+        if (!grid_sync<kSnap>(gs, nb, h.limit, snap, bar)) return;
+        // the frontier, with its histogram rows (buckets 1..core[v]) cleared
+        const int lane = lane_id();
+        for (long long base = (long long)blockIdx.x * kBlock; base < na; base += (long long)gridDim.x * kBlock) {
+            const long long i = base + threadIdx.x;
+            int v = 0, c = 0;
+            long long rs = 0, d = 0;
+            bool in = false;
+            if (i < na) {
+                v = a.A[cur][i];
+                rs = a.AR[cur][i];
+                d = (long long)h.off[v + 1] - rs;
+                c = h.core[v];
+                in = a.cnt_mode ? a.cnt[v] < c : true;
+            }
+            if (in && c <= kSmall)
+                for (int b = 0; b < c; ++b) h.histo[rs + b] = 0;
+            unsigned long long mm = __ballot(in && c > kSmall);
+            while (mm) {
+                const int l = __ffsll(mm) - 1;
+                mm &= mm - 1;
+                const int cc = __shfl(c, l);
+                const long long ra = __shfl(rs, l);
+                for (int b = lane; b < cc; b += kWave) h.histo[ra + b] = 0;
+            }
+            wave_push_packed(in, v, rs, d, &gs->ctr[FET].v, 0, h.F[0], h.FE[0], h.FR[0]);
+        }
+        if (!grid_sync<kSnap>(gs, nb, h.limit, snap, bar)) return;
+        const long long nf = (long long)(snap[FET] & kSlotMask);
+        const long long ef = (long long)(snap[FET] >> kSlotBits);
+        if (nf == 0) break;  // CntCore: nobody changes
+        ++rounds_run;
+        hidx += nf;
+        // Step I: bucket min(core[u], core[v]) of v counts neighbour u
+        nedge += lead ? ef : 0;
+        edge_balanced(h.F[0], h.FE[0], h.FR[0], nullptr, nullptr, 0, nf, 0ll, ef, h.cols, nullptr, eb,
+                      [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR], EbLds &L,
+                          const int (&)[kEbR]) {
+                          int cu[kEbR];
+#pragma unroll
+                          for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? h.core[u[r]] : 0;
+#pragma unroll
+                          for (int r = 0; r < kEbR; ++r) {
+                              if (!act[r]) continue;
+                              const int cv = h.core[L.id[own[r]]];
+                              const int b = min(max(cu[r], 1), cv);
+                              atomicAdd(&h.histo[L.rs[own[r]] + b - 1], 1);
+                              ++natom;
+                          }
+                      });
+        if (!grid_sync<kSnap>(gs, nb, h.limit, snap, bar)) return;
+        // Step II: the new values (core, P0) and the old ones (oldcore, P1)
+        const unsigned long long hs0 = snap[HS_TAIL];
+        sum_histo<Off>(h, h.F[0], h.FR[0], nf, nbuck);
+        if (!grid_sync<kSnap>(gs, nb, h.limit, snap, bar)) return;
+        sum_heavy<Off>(h, h.F[0], h.FR[0], hs0, snap[HS_TAIL], part, &first_ok);
+        if (!grid_sync<kSnap>(gs, nb, h.limit, snap, bar)) return;
+        // the neighbours of the vertices that changed form the next active list
+        long long emark = 0;
+        edge_balanced(h.F[0], h.FE[0], h.FR[0], h.P0, h.P1, 0, nf, 0ll, ef, h.cols, nullptr, eb,
+                      [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR], EbLds &L,
+                          const int (&)[kEbR]) {
+#pragma unroll
+                          for (int r = 0; r < kEbR; ++r) {
+                              bool first = false;
+                              if (act[r] && L.p0[own[r]] != L.p1[own[r]]) {
+                                  ++emark;
+                                  first = atomicExch(&a.mark[u[r]], t) != t;
+                                  if (first) a.cnt[u[r]] = 0;
+                              }
+                              long long rs = 0, d = 0;
+                              if (first) {
+                                  rs = (long long)h.off[u[r]];
+                                  d = (long long)h.off[u[r] + 1] - rs;
+                              }
+                              wave_push_packed(first, u[r], rs, d, &gs->ctr[IC_AET].v, 0, a.A[nxt], a.AE[nxt],
+                                               a.AR[nxt]);
+                          }
+                      });
+        nedge += emark;
+        if (!grid_sync<kSnap>(gs, nb, h.limit, snap, bar)) return;
+        na = (long long)(snap[IC_AET] & kSlotMask);
+        ea = (long long)(snap[IC_AET] >> kSlotBits);
+        if (na > 0) ++rounds_changed;
+        activations += na;
+    }
+    flush_count(natom, &gs->ctr[IC_ATOM].v);
+    flush_count(nbuck, &gs->ctr[N_BUCKETS].v);
+    flush_count(nedge, &gs->ctr[IC_EDGES].v);
+    if (lead) {
+        st->rounds.v = (unsigned long long)rounds_changed;
+        st->first_frontier.v = (unsigned long long)rounds_run;
+        st->frontier_total.v = (unsigned long long)hidx;
+        st->phase[0].v = (unsigned long long)active;
+        st->phase[1].v = (unsigned long long)activations;
+    }
+}
 }  // namespace
 
 size_t histocore_ws_bytes(int64_t n, int64_t m) {
@@ -598,5 +783,94 @@ template int run_histocore<int32_t>(const int32_t *, const int32_t *, int64_t, i
                                     void *, size_t, pico_stats *, hipStream_t, const int32_t *, int);
 template int run_histocore<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *,
                                     void *, size_t, pico_stats *, hipStream_t, const int32_t *, int);
+
+size_t index2core_ws_bytes(int64_t n, int64_t m) {
+    return histocore_ws_bytes(n, m) + carve_bytes(n, 4) * 4 + carve_bytes(n, 8) * 4;
+}
+
+template <typename Off>
+int run_index2core(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
+                   size_t ws_bytes, pico_stats *stats, hipStream_t stream, int cnt_mode) {
+    if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
+        set_error("m=%lld too large for the packed frontier counter", (long long)m);
+        return PICO_ENOTSUP;
+    }
+    Carve cv{static_cast<char *>(ws), 0, ws_bytes};
+    IcArgs<Off> a;
+    HcArgs<Off> &h = a.h;
+    h.off = off;
+    h.cols = cols;
+    h.n = n;
+    h.core = out;
+    h.histo = cv.take<int32_t>(m);
+    h.ndeg = nullptr;
+    h.oldcore = cv.take<int32_t>(n);
+    h.F[0] = cv.take<int32_t>(n);
+    h.FE[0] = cv.take<long long>(n);
+    h.FR[0] = cv.take<long long>(n);
+    h.F[1] = nullptr;
+    h.FE[1] = nullptr;
+    h.FR[1] = nullptr;
+    h.P0 = cv.take<int32_t>(n);
+    h.P1 = cv.take<int32_t>(n);
+    h.HS = cv.take<int32_t>(n);
+    h.hcap = 0;
+    h.H = nullptr;
+    h.st = cv.take<HcState>(1);
+    h.limit = wall_ticks(20.0);
+    h.warm = nullptr;
+    h.warm_add = 0;
+    a.cnt = cv.take<int32_t>(n);
+    a.mark = cv.take<int32_t>(n);
+    for (int b = 0; b < 2; ++b) {
+        a.A[b] = cv.take<int32_t>(n);
+        a.AE[b] = cv.take<long long>(n);
+        a.AR[b] = cv.take<long long>(n);
+    }
+    a.cnt_mode = cnt_mode;
+    if ((m > 0 && !h.histo) || !h.oldcore || !h.F[0] || !h.FE[0] || !h.FR[0] || !h.P0 || !h.P1 || !h.HS ||
+        !h.st || !a.cnt || !a.mark || !a.A[0] || !a.A[1] || !a.AE[0] || !a.AE[1] || !a.AR[0] || !a.AR[1]) {
+        set_error("Index2core workspace too small (%zu bytes given, %zu needed)", ws_bytes,
+                  index2core_ws_bytes(n, m));
+        return PICO_ENOMEM;
+    }
+    int blocks = 0;
+    int rc = persistent_grid(reinterpret_cast<const void *>(ic_persistent<Off>), kBlock,
+                             tune_int("PICO_HC_BLOCKS_PER_CU", 2), grid_want_histocore(m), &blocks);
+    if (rc) return rc;
+    PICO_LAUNCH("hc_state_init", hc_state_init, dim3(1), dim3(kBlock), stream, h.st);
+    PICO_LAUNCH_CHECK();
+    void *args[] = {&a};
+    int rec = prof_begin(cnt_mode ? "cntcore_persistent" : "nbrcore_persistent", stream);
+    PICO_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(ic_persistent<Off>), dim3(blocks),
+                                            dim3(kBlock), args, 0, stream));
+    prof_end(rec, stream);
+    HcState *hs = static_cast<HcState *>(host_scratch(sizeof(HcState)));
+    if (!hs) return PICO_EHIP;
+    PICO_HIP_TRY(hipMemcpyAsync(hs, h.st, sizeof(HcState), hipMemcpyDeviceToHost, stream));
+    PICO_HIP_TRY(hipStreamSynchronize(stream));
+    if (hs->g.error.v) {
+        set_error("Index2core kernel stopped (error %llu; grid of %d blocks)", (unsigned long long)hs->g.error.v,
+                  blocks);
+        return PICO_EHIP;
+    }
+    if (stats) {
+        stats->iterations = (int64_t)hs->rounds.v;         // rounds that changed a value (l2)
+        stats->sub_rounds = (int64_t)hs->first_frontier.v;  // rounds that computed h-indexes
+        stats->scans = (int64_t)hs->phase[0].v;             // active vertices, summed over rounds
+        stats->frontier_total = (int64_t)hs->frontier_total.v;  // h-indexes computed
+        stats->k_max = 0;
+        stats->edges_scanned = (int64_t)hs->g.ctr[IC_EDGES].v;
+        stats->atomics = (int64_t)hs->g.ctr[IC_ATOM].v;
+        stats->buckets_scanned = (int64_t)hs->g.ctr[N_BUCKETS].v;
+        stats->pushes_dynamic = (int64_t)hs->phase[1].v;  // activations after the first round
+    }
+    return PICO_OK;
+}
+
+template int run_index2core<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int32_t *, void *,
+                                     size_t, pico_stats *, hipStream_t, int);
+template int run_index2core<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *, void *,
+                                     size_t, pico_stats *, hipStream_t, int);
 
 }  // namespace pico

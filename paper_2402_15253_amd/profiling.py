@@ -72,8 +72,10 @@ def kernel_stats(d: str) -> dict:
 
 def counter_per_dispatch(d: str, counter: str) -> dict:
     """Mean counter value (KiB) per dispatch of each decomposition kernel, and
-    the calibration copy's value ('copy': the largest copyBuffer dispatch)."""
-    acc, copy_max = {}, 0.0
+    the calibration copy's value ('copy': the last copyBuffer dispatch --
+    bench.py's --copy-calibration copy runs after everything it measures, and
+    input generation may dispatch larger copies before it)."""
+    acc, copy_last = {}, (-1, 0.0)
     with open(_find(d, "counter_collection.csv")) as f:
         for row in csv.DictReader(f):
             if row.get("Counter_Name") != counter:
@@ -84,9 +86,11 @@ def counter_per_dispatch(d: str, counter: str) -> dict:
                     s, c = acc.get(k, (0.0, 0))
                     acc[k] = (s + val, c + 1)
             if COPY_KERNEL in name:
-                copy_max = max(copy_max, val)
+                did = int(row.get("Dispatch_Id") or 0)
+                if did >= copy_last[0]:
+                    copy_last = (did, val)
     out = {k: s / c for k, (s, c) in acc.items()}
-    out["copy"] = copy_max
+    out["copy"] = copy_last[1]
     return out
 
 

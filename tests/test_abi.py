@@ -75,6 +75,10 @@ def test_argument_errors_need_no_device():
     assert pico.pico_coreness(None, None, 0, 0, pico.PICO_ALGO_AUTO, None) == pico.PICO_OK
     assert pico.pico_workspace_bytes(1000, 8000, pico.PICO_ALGO_AUTO) >= max(
         pico.pico_workspace_bytes(1000, 8000, a) for a in (pico.PICO_ALGO_PEELONE, pico.PICO_ALGO_HISTOCORE))
+    # Index2core baselines: grid path only
+    for alg in (pico.PICO_ALGO_CNTCORE, pico.PICO_ALGO_NBRCORE):
+        assert pico.pico_coreness(None, None, 0, 0, alg | pico.PICO_PATH_WG, None) == pico.PICO_ENOTSUP
+        assert pico.pico_workspace_bytes(1000, 8000, alg) >= pico.pico_workspace_bytes(1000, 8000, hc_)
     # core maintenance: HistoCore only, bounds required, bound_add >= 0
     up = pico.pico_coreness_update
     hc = pico.PICO_ALGO_HISTOCORE

@@ -1,0 +1,52 @@
+"""GPU CntCore and NbrCore (the Index2core baselines of Table VIII) against
+the oracle: the coreness bit for bit, and every work count exactly (the rounds
+are synchronous, so active sets, frontiers, h-index computations and
+adjacency reads are functions of the graph)."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_2402_15253_amd as pico
+
+pytestmark = pytest.mark.gpu
+
+GRAPHS = [lambda: gg.g1(), lambda: gg.path(1001), lambda: gg.complete(300), lambda: gg.star(5000),
+          lambda: gg.rmat(12, 16, 101), lambda: gg.er_gnp(3000, 9.0, 102),
+          lambda: gg.rmat(14, 16, 103).with_offsets(torch.int64),
+          lambda: gg.scaled_rmat_block(13, 104, 300, 0.6, 105),
+          lambda: gg.disjoint_union(gg.complete(40), gg.cycle(50), gg.empty_graph(5), gg.hypercube(7))]
+
+
+@pytest.mark.parametrize("variant", ["cntcore", "nbrcore"])
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_counts_match_oracle(gi, variant):
+    g = GRAPHS[gi]()
+    print(f"case {g.name} n={g.n} m={g.m} {variant}", flush=True)
+    want, c = oracle.index2core(g.offsets, g.cols, variant)
+    assert np.array_equal(want, oracle.bz_coreness(g.offsets, g.cols))
+    d = g.to("cuda")
+    got, st = pico.coreness(d.offsets, d.cols, variant, with_stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    assert st["iterations"] == c["rounds_changed"]
+    assert st["sub_rounds"] == c["rounds_run"]
+    assert st["scans"] == c["active"]
+    assert st["frontier_total"] == c["hindex_computed"]
+    assert st["edges_scanned"] == c["edges_cnt"] + c["edges_hindex"] + c["edges_mark"]
+    assert st["pushes_dynamic"] == c["activations"]
+    assert st["atomics"] >= c["edges_hindex"]
+
+
+def test_histocore_reads_fewer_edges():
+    """The point of Table VIII: with the same rounds, HistoCore reads each
+    frontier vertex's row once per round where CntCore reads it three times
+    (cnt, histogram, marking) and NbrCore recomputes whole neighbourhoods."""
+    g = gg.rmat(15, 16, 106).to("cuda")
+    st = {}
+    for v in ("histocore", "cntcore", "nbrcore"):
+        _, st[v] = pico.coreness(g.offsets, g.cols, v, with_stats=True)
+    assert st["histocore"]["iterations"] == st["cntcore"]["iterations"] == st["nbrcore"]["iterations"]
+    assert st["histocore"]["frontier_total"] == st["cntcore"]["frontier_total"] < st["nbrcore"]["frontier_total"]
+    assert st["histocore"]["edges_scanned"] < st["cntcore"]["edges_scanned"]

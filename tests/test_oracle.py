@@ -390,3 +390,42 @@ def test_static_peel_matches_bz_and_needs_more_iterations(seed):
     x, it = oracle.peel_static(g.offsets, g.cols)
     assert np.array_equal(x, want)
     assert it >= len(np.unique(want[want > 0]))
+
+
+# ---------------------------------------------------------------- CntCore and NbrCore (Table VIII's baselines)
+# Pins: the coreness (BZ); Theorem 2 -- CntCore's frontier in each round is
+# exactly the set of vertices whose value the synchronous h-index iteration
+# lowers, so its rounds and h-index computations equal hindex_jacobi's rounds
+# and changed counts; NbrCore recomputes every active vertex and needs one
+# more round to see that nothing changes; G1's narrative (Section II-C: only
+# v3 and v5 change, v5 from 5 to 2; nobody changes afterwards).
+
+I2C_GRAPHS = [lambda: gg.g1(), lambda: gg.rmat(11, 8, 91), lambda: gg.er_gnp(1500, 7.0, 92),
+              lambda: gg.path(101), lambda: gg.complete(20), lambda: gg.star(50),
+              lambda: gg.disjoint_union(gg.complete(9), gg.cycle(12), gg.empty_graph(3), gg.hypercube(5))]
+
+
+@pytest.mark.parametrize("gi", range(len(I2C_GRAPHS)))
+def test_cntcore_nbrcore(gi):
+    g = I2C_GRAPHS[gi]()
+    want = oracle.bz_coreness(g.offsets, g.cols)
+    _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
+    xc, c = oracle.index2core(g.offsets, g.cols, "cntcore")
+    xn, nb = oracle.index2core(g.offsets, g.cols, "nbrcore")
+    assert np.array_equal(xc, want) and np.array_equal(xn, want)
+    assert c["rounds_changed"] == nb["rounds_changed"] == len(per_round)
+    assert c["hindex_computed"] == sum(per_round)
+    live = int((g.degrees() > 0).sum())
+    assert nb["hindex_computed"] == nb["active"] >= live
+    assert nb["rounds_run"] == (len(per_round) + 1 if live else 0)
+    assert c["edges_hindex"] == c["edges_mark"] == nb["edges_mark"]
+    assert c["activations"] == nb["activations"] and c["active"] == nb["active"]
+    assert nb["edges_hindex"] == c["edges_cnt"]  # same active sets, read once each
+
+
+def test_cntcore_g1(golden_g1):
+    g = gg.g1()
+    _, c = oracle.index2core(g.offsets, g.cols, "cntcore")
+    under = [int(v) for v in golden_g1["under_core"]]  # v3, v5: the only vertices that change
+    assert c["rounds_changed"] == 1 and c["hindex_computed"] == len(under) == 2
+    assert c["active"] == 6 + 6  # round 1: every vertex; round 2: the neighbours of v3 and v5
