@@ -676,7 +676,7 @@ def main():
     ablations = None
     if not args.no_ablations and "peelone" in algos:
         ablations = {}
-        for variant in ("peelone", "peelone-static", "peelone-rollback"):
+        for variant in ("peelone", "peelone-static", "peelone-rollback", "gpp"):
             code = pico.algo_code(variant, g.offsets)
             vout = torch.empty(n, dtype=torch.int32, device=dev)
             vst = pico.PicoStats()

@@ -97,9 +97,14 @@ enum {
      *     iteration (Table IV's l1 for this variant).
      *   PICO_PO_ROLLBACK: the decrement of atomicAdd-rollback methods
      *     (Section III-B) -- a decrement landing at or below k is undone by an
-     *     atomic add; stats.atomics counts both. */
+     *     atomic add; stats.atomics counts both.
+     *   PICO_PO_GPP: General Parallel Peel (Alg. 3, Section II-C), the
+     *     GPP baseline of Section V -- no dynamic frontier, every neighbour not yet
+     *     removed decremented, k from 1 advancing by one when a scan finds
+     *     nobody; stats.iterations counts every scan. */
     PICO_PO_STATIC = 0x800,
-    PICO_PO_ROLLBACK = 0x1000
+    PICO_PO_ROLLBACK = 0x1000,
+    PICO_PO_GPP = 0x2000
 };
 
 /* Run statistics (all counts over the whole call). */

@@ -13,6 +13,8 @@ Routines (each cites the passage of the paper it follows):
 * ``index2core``     -- CntCore (Section IV-A, Alg. 5) and NbrCore (the
   Index2core baseline of Section V) in synchronous rounds, with work counts
   (C).
+* ``peel_gpp``       -- General Parallel Peel (Section II-C, Alg. 3; the GPP
+  baseline of Section V), serially, with its iteration count (C).
 * ``peel_static``    -- PeelOne without the dynamic frontier (the variant of
   Table IV), serially, with its iteration count (C).
 * ``hindex_jacobi_from`` -- the same iteration started from upper bounds of
@@ -81,6 +83,9 @@ def _load():
         lib.oracle_index2core.restype = ctypes.c_int
         lib.oracle_index2core.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_peel_gpp.restype = ctypes.c_int64
+        lib.oracle_peel_gpp.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
         lib.oracle_peel_static.restype = ctypes.c_int64
         lib.oracle_peel_static.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]
@@ -156,6 +161,21 @@ def index2core(offsets, cols, variant: str):
     if r < 0:
         raise RuntimeError(f"oracle_index2core failed with {r}")
     return x, dict(zip(INDEX2CORE_COUNTS, (int(v) for v in out)))
+
+
+def peel_gpp(offsets, cols):
+    """General Parallel Peel (Alg. 3, Section II-C), serially: returns
+    (coreness, iterations, decrements), every scan an iteration (k from 1, +1
+    after a scan that finds nobody), one decrement per edge from a removed
+    vertex to a residual one."""
+    off, adj = _csr_np(offsets, cols)
+    n = off.shape[0] - 1
+    x = np.zeros(max(n, 0), dtype=np.int32)
+    dec = np.zeros(1, dtype=np.int64)
+    r = _load().oracle_peel_gpp(n, _ptr(off), _ptr(adj) if adj.size else None, _ptr(x), _ptr(dec))
+    if r < 0:
+        raise RuntimeError(f"oracle_peel_gpp failed with {r}")
+    return x, int(r), int(dec[0])
 
 
 def peel_static(offsets, cols):

@@ -20,7 +20,7 @@ import torch  # loaded first so the library binds to the HIP runtime torch uses
 __all__ = [
     "PICO_OK", "PICO_EINVAL", "PICO_ENOMEM", "PICO_EHIP", "PICO_ENOTSUP", "PICO_EBADCSR",
     "PICO_ALGO_PEELONE", "PICO_ALGO_HISTOCORE", "PICO_OFFSETS_I64", "PICO_PATH_GRID", "PICO_PATH_WG",
-    "PICO_PO_STATIC", "PICO_PO_ROLLBACK", "VARIANTS", "PICO_ALGO_CNTCORE", "PICO_ALGO_NBRCORE",
+    "PICO_PO_STATIC", "PICO_PO_ROLLBACK", "PICO_PO_GPP", "VARIANTS", "PICO_ALGO_CNTCORE", "PICO_ALGO_NBRCORE",
     "PATHS", "PicoError", "PicoStats",
     "pico_coreness", "pico_coreness_ws", "pico_coreness_update", "coreness_update",
     "pico_select_algorithm", "select_algorithm", "PICO_ALGO_AUTO", "SINGLE_ALGOS", "ALGO_NAMES",
@@ -37,7 +37,7 @@ __all__ = [
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
 PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE, PICO_ALGO_AUTO, PICO_OFFSETS_I64 = 0, 1, 2, 0x100
 PICO_PATH_GRID, PICO_PATH_WG = 0x200, 0x400
-PICO_PO_STATIC, PICO_PO_ROLLBACK = 0x800, 0x1000
+PICO_PO_STATIC, PICO_PO_ROLLBACK, PICO_PO_GPP = 0x800, 0x1000, 0x2000
 PATHS = {None: 0, "auto": 0, "grid": PICO_PATH_GRID, "wg": PICO_PATH_WG}
 ALGOS = {"peelone": PICO_ALGO_PEELONE, "histocore": PICO_ALGO_HISTOCORE}
 # single-graph calls may also ask for the per-graph choice between the two
@@ -47,6 +47,7 @@ ALGO_NAMES = {PICO_ALGO_PEELONE: "peelone", PICO_ALGO_HISTOCORE: "histocore"}
 PICO_ALGO_CNTCORE, PICO_ALGO_NBRCORE = 3, 4
 VARIANTS = {"peelone-static": PICO_ALGO_PEELONE | PICO_PO_STATIC,
             "peelone-rollback": PICO_ALGO_PEELONE | PICO_PO_ROLLBACK,
+            "gpp": PICO_ALGO_PEELONE | PICO_PO_GPP,
             # Index2core baselines (Table VIII): every h-index rebuilt from the neighbours
             "cntcore": PICO_ALGO_CNTCORE, "nbrcore": PICO_ALGO_NBRCORE}
 

@@ -150,7 +150,7 @@ int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int a
         return PICO_ENOTSUP;
     }
     if ((algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64 | PICO_PATH_GRID | PICO_PATH_WG | PICO_PO_STATIC |
-                  PICO_PO_ROLLBACK)) != 0) {
+                  PICO_PO_ROLLBACK | PICO_PO_GPP)) != 0) {
         set_error("unknown flag bits in algo 0x%x", algo);
         return PICO_EINVAL;
     }
@@ -158,9 +158,10 @@ int check_args(const void *off, const int32_t *cols, int64_t n, int64_t m, int a
         set_error("PICO_PATH_GRID and PICO_PATH_WG are exclusive");
         return PICO_EINVAL;
     }
-    if (algo & (PICO_PO_STATIC | PICO_PO_ROLLBACK)) {
-        if (a != PICO_ALGO_PEELONE || ((algo & PICO_PO_STATIC) && (algo & PICO_PO_ROLLBACK))) {
-            set_error("PICO_PO_STATIC / PICO_PO_ROLLBACK: one of them, with PeelOne only");
+    const int abl = algo & (PICO_PO_STATIC | PICO_PO_ROLLBACK | PICO_PO_GPP);
+    if (abl) {
+        if (a != PICO_ALGO_PEELONE || (abl & (abl - 1))) {
+            set_error("PICO_PO_STATIC / PICO_PO_ROLLBACK / PICO_PO_GPP: one of them, with PeelOne only");
             return PICO_EINVAL;
         }
         if (algo & PICO_PATH_WG) {
@@ -238,7 +239,7 @@ int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int alg
                    : run_small<int32_t>(static_cast<const int32_t *>(off), cols, n, m, algo, out, ws,
                                         ws_bytes, st, s, warm, warm_add);
     if ((algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE) {
-        const int mode = (algo & PICO_PO_STATIC) ? 1 : (algo & PICO_PO_ROLLBACK) ? 2 : 0;
+        const int mode = (algo & PICO_PO_STATIC) ? 1 : (algo & PICO_PO_ROLLBACK) ? 2 : (algo & PICO_PO_GPP) ? 3 : 0;
         return i64 ? run_peelone<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
                                           ws_bytes, st, s, mode)
                    : run_peelone<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws,

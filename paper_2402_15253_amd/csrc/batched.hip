@@ -1121,7 +1121,7 @@ size_t small_ws_bytes(int64_t n, int64_t m, int algo) {
 
 int small_path(int64_t n, int64_t m, int algo, bool *use) {
     *use = false;
-    if (algo & (PICO_PATH_GRID | PICO_PO_STATIC | PICO_PO_ROLLBACK)) return PICO_OK;
+    if (algo & (PICO_PATH_GRID | PICO_PO_STATIC | PICO_PO_ROLLBACK | PICO_PO_GPP)) return PICO_OK;
     const bool forced = (algo & PICO_PATH_WG) != 0;
     if (!forced && m > small_max_edges()) return PICO_OK;
     int cap = 0;

@@ -578,7 +578,8 @@ size_t peelone_ws_bytes(int64_t n, int64_t m);
 size_t histocore_ws_bytes(int64_t n, int64_t m);
 
 // mode: 0 = Alg. 4 (assertion, dynamic frontier); 1 = no dynamic frontier;
-// 2 = fetch-and-add rollback decrement (the paper's comparison variants).
+// 2 = fetch-and-add rollback decrement; 3 = General Parallel Peel (the
+// paper's comparison variants).
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
                 void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream, int mode = 0);

@@ -71,7 +71,12 @@ constexpr int kTile = kBlock * 8;  // scan items per block step
 //   kRollback -- the decrement of PP-dyn style methods (Section III-B): a
 //                fetch-and-subtract that lands at or below k is undone with a
 //                fetch-and-add, each counted as an atomic.
-enum { kDynamic = 0, kStatic = 1, kRollback = 2 };
+//   kGpp      -- General Parallel Peel (Alg. 3, Section II-C; the GPP
+//                baseline of Section V): as kStatic, but every neighbour not
+//                yet removed is decremented (the removal flag is the filter,
+//                not the value), and k starts at 1 and advances by one when
+//                a scan finds nobody, each such scan an iteration.
+enum { kDynamic = 0, kStatic = 1, kRollback = 2, kGpp = 3 };
 
 // Cumulative counters of the grid state.  QET packs (edges << 31) | slots of
 // the global frontier list.
@@ -205,22 +210,26 @@ __device__ __forceinline__ bool claim_vertex(int32_t *out, int v, int k) {
 
 // kEbR edges per thread of the scatter (Alg. 4, graph operator): the filter
 // reads and the decrements of all edges are issued before any result is used.
-template <typename Off>
+// kMode: the variant this kernel is compiled for (each its own kernel, so
+// Alg. 4's carries none of the ablations' code).
+template <typename Off, int kMode>
 __device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kEbR], PoCtx<Off> &c) {
+    constexpr int mode = kMode;
+    const bool gpp = mode == kGpp;
     int cu[kEbR];
 #pragma unroll
-    for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? c.core[u[r]] : 0;
+    for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? (gpp ? c.out[u[r]] : c.core[u[r]]) : 0;
     int old[kEbR];
 #pragma unroll
     for (int r = 0; r < kEbR; ++r) {
         old[r] = 0;
-        if (act[r] && cu[r] > c.k) {
+        if (act[r] && (gpp ? cu[r] == -1 : cu[r] > c.k)) {
             old[r] = atomicSub(&c.core[u[r]], 1);
             ++c.natom;
         }
     }
-    if (c.mode == kStatic) return;  // lowered vertices wait for the next scan
-    if (c.mode == kRollback) {
+    if (mode == kStatic || gpp) return;  // lowered vertices wait for the next scan
+    if (mode == kRollback) {
 #pragma unroll
         for (int r = 0; r < kEbR; ++r) {
             if (act[r] && cu[r] > c.k && old[r] <= c.k) {
@@ -242,7 +251,7 @@ __device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kE
 // Expand the workgroup's LDS queue until it is empty: a batch of up to 256
 // queued vertices at a time, expanded here when its rows hold at most
 // kLocalMax edges, otherwise sent to the global list for the next round.
-template <typename Off>
+template <typename Off, int kMode>
 __device__ void drain_lds(const PoArgs<Off> &a, PoCtx<Off> &c, ExpandLds &X) {
     while (true) {
         __syncthreads();
@@ -269,7 +278,7 @@ __device__ void drain_lds(const PoArgs<Off> &a, PoCtx<Off> &c, ExpandLds &X) {
         } else {
             block_expand<kEbR>((int)d, rs, 0, 0, a.cols, X,
                                [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&)[kEbR]) {
-                                   relax<Off>(act, u, c);
+                                   relax<Off, kMode>(act, u, c);
                                });
         }
         __syncthreads();
@@ -316,7 +325,7 @@ __device__ void po_init(const PoArgs<Off> &a, unsigned long long *na_ctr, unsign
 // is recorded.  A tile's claimed frontier stays in the workgroup's LDS queue
 // while the workgroup's share is small (expanded right after the scan);
 // otherwise it goes to the global list for an edge-balanced round.
-template <typename Off>
+template <typename Off, int kMode>
 __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__restrict__ src,
                         long long nsrc, int32_t *__restrict__ dst, unsigned long long *na_ctr,
                         unsigned long long *mn_ctr, unsigned long long *nf_ctr, int *lds,
@@ -344,7 +353,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
                 sv |= 1u << r;
                 lmin = min(lmin, cv);
             }
-            if (cv == k || (c.mode == kStatic && v >= 0 && cv < k)) cand |= 1u << r;
+            if (cv == k || ((kMode == kStatic || kMode == kGpp) && v >= 0 && cv < k)) cand |= 1u << r;
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -367,7 +376,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
         if (tf == 0) continue;
         claimed += tf;
         const unsigned tail = *c.lq.tail, keep = *c.lq.keep;
-        const bool local = c.mode != kStatic && local_edges + te <= kLocalMax &&
+        const bool local = kMode != kStatic && kMode != kGpp && local_edges + te <= kLocalMax &&
                            tail + tf - keep <= (unsigned)kLq;
         if (local) {
             local_edges += te;
@@ -409,19 +418,20 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
 
 // One edge-balanced round of level k over global frontier entries [q0, q1)
 // (edge space [e0, e1)), then this workgroup's LDS queue.
-template <typename Off>
+template <typename Off, int kMode>
 __device__ void po_round(const PoArgs<Off> &a, PoCtx<Off> &c, unsigned long long q0,
                          unsigned long long q1, unsigned long long e0, unsigned long long e1,
                          EbLds &E, ExpandLds &X) {
     edge_balanced(a.Q, a.QE, a.QR, nullptr, nullptr, (long long)q0, (long long)q1, (long long)e0,
                   (long long)e1, a.cols, nullptr, E,
                   [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&)[kEbR], EbLds &,
-                      const int (&)[kEbR]) { relax<Off>(act, u, c); });
-    drain_lds<Off>(a, c, X);
+                      const int (&)[kEbR]) { relax<Off, kMode>(act, u, c); });
+    drain_lds<Off, kMode>(a, c, X);
 }
 
-template <typename Off>
+template <typename Off, int kMode>
 __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
+    constexpr int mode = kMode;
     __shared__ int lds[kWavesPerBlock];
     __shared__ long long lds_l[kWavesPerBlock];
     __shared__ unsigned long long lds64[1];
@@ -436,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     unsigned long long bar = 0;
     if (threadIdx.x == 0) lq_take = lq_tail = lq_keep = 0;
     PoCtx<Off> c{a.off, a.core, a.out, a.Q, a.QE, a.QR, &gs->ctr[QET].v,
-                 LdsQueue{lq_buf, &lq_take, &lq_tail, &lq_keep}, 0, 0, 0, a.mode};
+                 LdsQueue{lq_buf, &lq_take, &lq_tail, &lq_keep}, 0, 0, 0, mode};
 
     const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
     PhaseClock clk;
@@ -447,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     if (timer) clk.lap(&st->phase[0].v);
     const unsigned long long peelable = ld_rlx(&st->na[0].v);
     long long nprev = (long long)peelable;
-    c.k = (int)ld_rlx(&st->mn[0].v);
+    c.k = mode == kGpp ? 1 : (int)ld_rlx(&st->mn[0].v);
     unsigned long long q_end = 0, e_end = 0;  // global list consumed so far
     long long levels = 0, scans = 0, rounds = 0;
     int kmax = 0;
@@ -460,9 +470,9 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
             st_rlx(&st->mn[(j + 1) % 3].v, (unsigned long long)INT_MAX);
             st_rlx(&st->nf[(j + 1) % 3].v, 0ull);
         }
-        po_scan<Off>(a, c, src, nprev, dst, &st->na[j % 3].v, &st->mn[j % 3].v, &st->nf[j % 3].v,
+        po_scan<Off, kMode>(a, c, src, nprev, dst, &st->na[j % 3].v, &st->mn[j % 3].v, &st->nf[j % 3].v,
                      lds, lds_l, lds64);
-        drain_lds<Off>(a, c, xl);
+        drain_lds<Off, kMode>(a, c, xl);
         ++scans;
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         const unsigned long long t_scan = wall_clock64();
@@ -471,13 +481,13 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
         nprev = (long long)ld_rlx(&st->na[j % 3].v);
         if (ld_rlx(&st->nf[j % 3].v) == 0ull) {  // empty level: jump to the smallest value left
             if (nprev == 0) break;
-            c.k = (int)ld_rlx(&st->mn[j % 3].v);
+            c.k = mode == kGpp ? c.k + 1 : (int)ld_rlx(&st->mn[j % 3].v);
             continue;
         }
         unsigned long long q0 = q_end, e0 = e_end;
         unsigned long long q1 = snap[QET] & kSlotMask, e1 = snap[QET] >> kSlotBits;
         while (q0 < q1) {
-            po_round<Off>(a, c, q0, q1, e0, e1, eb, xl);
+            po_round<Off, kMode>(a, c, q0, q1, e0, e1, eb, xl);
             ++rounds;
             if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
             q0 = q1;
@@ -502,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
         ++levels;
         kmax = c.k;
         if (nprev == 0) break;  // no survivor left after this level's scan: all claimed
-        if (a.mode != kStatic) c.k += 1;  // static: rescan the same level
+        if (mode != kStatic && mode != kGpp) c.k += 1;  // static, GPP: rescan the same level
     }
     long long t = wave_sum64(c.natom);
     if (lane_id() == 0 && t) atomicAdd(&gs->ctr[N_ATOM].v, (unsigned long long)t);
@@ -563,14 +573,18 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     // of edges the edge rounds dominate and a second workgroup per CU hides
     // more gather latency (RMAT-26: 142 ms at one, 133.5 at two, 137.7 at four).
     const int per_cu_default = m >= (1ll << 28) ? 2 : 1;
-    int rc = persistent_grid(reinterpret_cast<const void *>(po_persistent<Off>), kBlock,
+    const void *kernel = mode == kStatic     ? reinterpret_cast<const void *>(po_persistent<Off, kStatic>)
+                         : mode == kRollback ? reinterpret_cast<const void *>(po_persistent<Off, kRollback>)
+                         : mode == kGpp      ? reinterpret_cast<const void *>(po_persistent<Off, kGpp>)
+                                             : reinterpret_cast<const void *>(po_persistent<Off, kDynamic>);
+    int rc = persistent_grid(kernel, kBlock,
                              tune_int("PICO_PO_BLOCKS_PER_CU", per_cu_default), grid_want_peelone(m), &blocks);
     if (rc) return rc;
     PICO_LAUNCH("po_state_init", po_state_init, dim3(1), dim3(kBlock), stream, a.st);
     PICO_LAUNCH_CHECK();
     void *args[] = {&a};
     int rec = prof_begin("po_persistent", stream);
-    PICO_HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(po_persistent<Off>),
+    PICO_HIP_TRY(hipLaunchCooperativeKernel(kernel,
                                             dim3(blocks), dim3(kBlock), args, 0, stream));
     prof_end(rec, stream);
 
@@ -602,7 +616,7 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
         return PICO_EHIP;
     }
     if (stats) {
-        stats->iterations = (int64_t)h->levels.v;
+        stats->iterations = (int64_t)(mode == kGpp ? h->scans.v : h->levels.v);  // GPP: every scan
         stats->sub_rounds = (int64_t)h->rounds.v;
         stats->scans = (int64_t)h->scans.v;
         stats->frontier_total = (int64_t)h->peelable.v;

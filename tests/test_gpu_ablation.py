@@ -1,4 +1,5 @@
-"""GPU PeelOne ablations (PICO_PO_STATIC, PICO_PO_ROLLBACK) against the oracle.
+"""GPU PeelOne ablations (PICO_PO_STATIC, PICO_PO_ROLLBACK, PICO_PO_GPP)
+against the oracle.
 
 Both give the coreness bit for bit.  Without the dynamic frontier the
 iteration count is fixed by the graph (every scan sees the values the
@@ -54,3 +55,20 @@ def test_rollback_matches_oracle(gi):
     _, st_dyn = _run(g, "peelone")
     assert st["iterations"] == st_dyn["iterations"]
     assert st["frontier_total"] == int((want > 0).sum())
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_gpp_matches_serial_schedule(gi):
+    """General Parallel Peel (Alg. 3): same coreness; its scans (k from 1, +1
+    after an empty scan) are fixed by the graph and equal the serial
+    oracle's, and so is its decrement count: every removed vertex decrements
+    each neighbour still residual, one atomic per such edge."""
+    g = GRAPHS[gi]()
+    print(f"case {g.name} n={g.n} m={g.m}", flush=True)
+    want, iters, decrements = oracle.peel_gpp(g.offsets, g.cols)
+    assert np.array_equal(want, oracle.bz_coreness(g.offsets, g.cols))
+    got, st = _run(g, "gpp")
+    assert np.array_equal(got, want)
+    assert st["iterations"] == iters
+    assert st["atomics"] == decrements  # removal flags are set before the decrements run
+    assert st["pushes_dynamic"] == 0

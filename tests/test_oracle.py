@@ -429,3 +429,39 @@ def test_cntcore_g1(golden_g1):
     under = [int(v) for v in golden_g1["under_core"]]  # v3, v5: the only vertices that change
     assert c["rounds_changed"] == 1 and c["hindex_computed"] == len(under) == 2
     assert c["active"] == 6 + 6  # round 1: every vertex; round 2: the neighbours of v3 and v5
+
+
+# ---------------------------------------------------------------- General Parallel Peel (Alg. 3)
+# Pins: BZ; closed forms (k starts at 1 and each scan that finds nobody raises
+# k by one and still counts); G1 from Section II-C's narrative of Alg. 3: in
+# the third iteration the degrees of v3 and v5 fall to 1 (below their
+# coreness 2), so they are removed in a fourth.
+
+def test_gpp_g1_narrative(golden_g1):
+    g = gg.g1()
+    x, it, dec = oracle.peel_gpp(g.offsets, g.cols)
+    assert x.tolist() == [int(c) for c in golden_g1["coreness"]]
+    # 1: v0, v1 (degree 1); 2: nobody at k = 1, k -> 2; 3: v2, v4, lowering v3, v5 to 1; 4: v3, v5
+    assert it == 4
+    # decrements: iteration 1 along v0-v5, v1-v5; iteration 3 along v2-v5, v2-v3, v4-v3,
+    # v4-v5; v3 and v5 go together in iteration 4, so their edge costs nothing
+    assert dec == 6
+
+
+def test_gpp_closed_forms():
+    for g, iters in ((gg.path(51), 26), (gg.complete(12), 11), (gg.cycle(30), 2), (gg.star(40), 2),
+                     (gg.empty_graph(3), 0), (gg.hypercube(4), 4)):
+        x, it, dec = oracle.peel_gpp(g.offsets, g.cols)
+        assert np.array_equal(x, oracle.bz_coreness(g.offsets, g.cols)), g.name
+        assert it == iters, g.name
+        assert dec <= g.m // 2  # at most one decrement per undirected edge
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_gpp_matches_bz(seed):
+    g = gg.rmat(11, 8, 70 + seed) if seed % 2 else gg.er_gnp(2000, 6.0, 70 + seed)
+    want = oracle.bz_coreness(g.offsets, g.cols)
+    x, it, _ = oracle.peel_gpp(g.offsets, g.cols)
+    assert np.array_equal(x, want)
+    _, it_static = oracle.peel_static(g.offsets, g.cols)
+    assert it >= it_static  # the same removals, plus a scan for every empty level
