@@ -689,7 +689,7 @@ def main():
             ablations[variant] = {"ms": round(min(times), 3), "iterations": vst.iterations,
                                   "atomics": vst.atomics, "pushes_dynamic": vst.pushes_dynamic,
                                   "identical": bool(torch.equal(vout, outs["peelone"]))}
-        # Index2core baselines against HistoCore (Table VIII): same rounds,
+        # Index2core baselines against HistoCore (Table VI): same rounds,
         # every h-index rebuilt from the neighbours
         i2c_bytes = max(pico.pico_workspace_bytes(n, m, pico.algo_code(v, g.offsets))
                         for v in ("cntcore", "nbrcore"))

@@ -64,7 +64,7 @@ enum {
     PICO_ALGO_AUTO = 2,       /* single-graph calls: PeelOne or HistoCore, chosen per
                                  graph by pico_select_algorithm's rule */
     /* Index2core baselines HistoCore is measured against (Section IV-A,
-     * Alg. 5; Section V, Table VIII), single-graph calls on the grid path:
+     * Alg. 5; Section V, Table VI), single-graph calls on the grid path:
      * synchronous rounds from the degrees with every h-index rebuilt from
      * the neighbours' values.  CntCore recomputes only vertices whose cnt
      * (neighbours valued >= their own value) fell below their value

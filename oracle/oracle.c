@@ -18,7 +18,7 @@
  *                          degree >= k.
  *  - oracle_peel_gpp:      General Parallel Peel, serially, counting scans.
  *  - oracle_index2core:    CntCore (Alg. 5) and NbrCore, synchronous rounds,
- *                          with their work counts (Table VIII's baselines).
+ *                          with their work counts (Table VI's baselines).
  *  - oracle_peel_static:   PeelOne without the dynamic frontier (Table IV's
  *                          variant), serially, counting its iterations.
  *  - oracle_hindex_jacobi_from: the same iteration started from upper bounds

@@ -48,7 +48,7 @@ PICO_ALGO_CNTCORE, PICO_ALGO_NBRCORE = 3, 4
 VARIANTS = {"peelone-static": PICO_ALGO_PEELONE | PICO_PO_STATIC,
             "peelone-rollback": PICO_ALGO_PEELONE | PICO_PO_ROLLBACK,
             "gpp": PICO_ALGO_PEELONE | PICO_PO_GPP,
-            # Index2core baselines (Table VIII): every h-index rebuilt from the neighbours
+            # Index2core baselines (Table VI): every h-index rebuilt from the neighbours
             "cntcore": PICO_ALGO_CNTCORE, "nbrcore": PICO_ALGO_NBRCORE}
 
 EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update", "pico_select_algorithm",

@@ -624,7 +624,7 @@ int run_batched(const long long *vptr, const long long *off, const int32_t *cols
                 hipStream_t stream);
 
 // CntCore (cnt_mode 1) or NbrCore (0): Index2core with every h-index rebuilt
-// from the neighbours' values, the baselines of the paper's Table VIII.
+// from the neighbours' values, the baselines of the paper's Table VI.
 size_t index2core_ws_bytes(int64_t n, int64_t m);
 template <typename Off>
 int run_index2core(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,

@@ -518,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
 // ---------------------------------------------------------------- CntCore / NbrCore
 //
 // The Index2core baselines the paper measures HistoCore against (Section
-// IV-A, Alg. 5, and Section V, Table VIII), in synchronous rounds from the
+// IV-A, Alg. 5, and Section V, Table VI), in synchronous rounds from the
 // degrees, with every h-index rebuilt from the neighbours' values (Step I
 // and Step II of Fig. 6 each time; no histogram carried between rounds):
 //   CntCore -- round t counts, for each vertex of the active set A (all

@@ -1,4 +1,4 @@
-"""GPU CntCore and NbrCore (the Index2core baselines of Table VIII) against
+"""GPU CntCore and NbrCore (the Index2core baselines of Table VI) against
 the oracle: the coreness bit for bit, and every work count exactly (the rounds
 are synchronous, so active sets, frontiers, h-index computations and
 adjacency reads are functions of the graph)."""
@@ -40,7 +40,7 @@ def test_counts_match_oracle(gi, variant):
 
 
 def test_histocore_reads_fewer_edges():
-    """The point of Table VIII: with the same rounds, HistoCore reads each
+    """The point of Table VI: with the same rounds, HistoCore reads each
     frontier vertex's row once per round where CntCore reads it three times
     (cnt, histogram, marking) and NbrCore recomputes whole neighbourhoods."""
     g = gg.rmat(15, 16, 106).to("cuda")

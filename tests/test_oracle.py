@@ -392,7 +392,7 @@ def test_static_peel_matches_bz_and_needs_more_iterations(seed):
     assert it >= len(np.unique(want[want > 0]))
 
 
-# ---------------------------------------------------------------- CntCore and NbrCore (Table VIII's baselines)
+# ---------------------------------------------------------------- CntCore and NbrCore (Table VI's baselines)
 # Pins: the coreness (BZ); Theorem 2 -- CntCore's frontier in each round is
 # exactly the set of vertices whose value the synchronous h-index iteration
 # lowers, so its rounds and h-index computations equal hindex_jacobi's rounds
