@@ -203,6 +203,9 @@ def bench_batched(args, pico, torch, np):
         if not args.no_tune:
             from paper_2402_15253_amd import autotune
             tune = autotune.tune_batched(b, a, order=order, log=log)
+        if args.help_min is not None:
+            tune = tune or pico.BatchTune()
+            tune.help_min_vertices = args.help_min
         wsb = pico.pico_batched_workspace_bytes(G, total_n, total_m, code)
         ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
         out_b = torch.empty(total_n, dtype=torch.int32, device=dev)
@@ -575,6 +578,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="batched: skip the autotuner and use the default launch parameters")
     ap.add_argument("--graphs", type=int, default=4096, help="batched: number of graphs")
+    ap.add_argument("--help-min", type=int, default=None,
+                    help="batched: vertices from which a graph takes helpers (-1 never; default: the "
+                         "library's or the autotuner's)")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched: skip the per-graph plain-call comparison (profiling runs)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")

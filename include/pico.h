@@ -239,10 +239,11 @@ typedef struct pico_batch_tune {
     int32_t sum_wave_min;   /* HistoCore SumHisto: a vertex whose value exceeds this
                                scans its buckets with a whole wave, smaller ones with
                                one thread; 0 = default (64) */
-    int32_t help_min_vertices; /* PeelOne graphs with at least this many vertices (and
-                               values in global memory) are decomposed by their
-                               workgroup with the help of idle workgroups of the same
-                               launch; 0 = default (32768), -1 = never */
+    int32_t help_min_vertices; /* graphs with at least this many vertices (and values
+                               in global memory) are decomposed by their workgroup
+                               with the help of idle workgroups of the same launch
+                               (PeelOne and HistoCore); 0 = default (32768),
+                               -1 = never */
 } pico_batch_tune;
 
 /* Statistics of one batched call (filled only if requested; the call then

@@ -68,14 +68,15 @@ def tune_batched(batch, algo: str, *, order=None, reps: int = 2, use_cache: bool
                  log=None) -> BatchTune:
     """Fastest BatchTune for this batch (device-resident) and algorithm:
     LDS tier and workgroups per CU first, then (HistoCore) the SumHisto wave
-    threshold at the best of those."""
+    threshold at the best of those, then whether large graphs take helpers
+    (the library default, or never)."""
     key = _key(batch, algo)
     cache = _load() if use_cache else {}
     if key in cache:
         c = cache[key]
         if log:
             log(f"autotune {algo}: cached {c}")
-        return BatchTune(c["lds_bytes"], c["blocks_per_cu"], c["sum_wave_min"])
+        return BatchTune(c["lds_bytes"], c["blocks_per_cu"], c["sum_wave_min"], c.get("help_min_vertices", 0))
     code = ALGOS[algo]
     G = batch.vptr.numel() - 1
     n, m = batch.offsets.numel() - 1, batch.cols.numel()
@@ -91,7 +92,7 @@ def tune_batched(batch, algo: str, *, order=None, reps: int = 2, use_cache: bool
                                    t, ws, wsb, st, stream)
         if rc != PICO_OK:
             raise PicoError(rc, pico_last_error())
-        eff = (st.lds_bytes, st.blocks_per_cu, t.sum_wave_min)
+        eff = (st.lds_bytes, st.blocks_per_cu, t.sum_wave_min, t.help_min_vertices)
         if eff in state["seen"]:  # clamped to a configuration already timed
             return state["seen"][eff]
         if state["ref"] is None:
@@ -108,8 +109,8 @@ def tune_batched(batch, algo: str, *, order=None, reps: int = 2, use_cache: bool
         dt = (time.perf_counter() - t0) / reps
         state["seen"][eff] = dt
         if log:
-            log(f"autotune {algo}: lds {eff[0]} blocks/CU {eff[1]} sum_wave_min {eff[2]}: "
-                f"{dt * 1e3:.2f} ms")
+            log(f"autotune {algo}: lds {eff[0]} blocks/CU {eff[1]} sum_wave_min {eff[2]} "
+                f"help_min {eff[3]}: {dt * 1e3:.2f} ms")
         return dt
 
     best, best_t = None, float("inf")
@@ -126,6 +127,12 @@ def tune_batched(batch, algo: str, *, order=None, reps: int = 2, use_cache: bool
             dt = measure(t)
             if dt < best_t:
                 best, best_t = t, dt
+    # helpers bound the time of a launch's largest graphs, but cost a little
+    # throughput when the launch is busy anyway
+    t = BatchTune(best.lds_bytes, best.blocks_per_cu, best.sum_wave_min, -1)
+    dt = measure(t)
+    if dt < best_t:
+        best, best_t = t, dt
     cache = _load() if use_cache else {}
     cache[key] = dict(best.as_dict(), ms=round(best_t * 1e3, 3))
     if use_cache:

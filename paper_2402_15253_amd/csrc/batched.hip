@@ -38,12 +38,15 @@ constexpr long long kSmallMaxEdgesDefault = 1ll << 14;  // one-workgroup path, s
 
 // ------------------------------------------------------------ helping
 //
-// A graph too large for one workgroup to finish quickly (PeelOne, values in
-// global memory, at least help_min vertices) is decomposed by the workgroup
-// that claimed it -- its leader -- with the help of workgroups that have no
-// graph left to claim.  The leader runs the level loop; each phase of it
-// (initialisation, a level's scan, a round of the level's drain) is a
-// parallel loop over an index range, cut into chunks.  For a phase worth
+// A graph too large for one workgroup to finish quickly (values in global
+// memory, at least help_min vertices) is decomposed by the workgroup that
+// claimed it -- its leader -- with the help of workgroups that have no graph
+// left to claim.  The leader runs the algorithm's outer loop; each phase of
+// it is a parallel loop over an index range, cut into chunks: for PeelOne
+// the initialisation, a level's scan and each round of the level's drain;
+// for HistoCore clearing the histogram, core = deg, InitHisto, the first
+// frontier, and per round SumHisto and then UpdateHisto (separate phases, so
+// the rounds stay synchronous), and the final copy to the output.  For a phase worth
 // sharing the leader publishes it in its job record and lists the record on
 // an open board; any idle workgroup claims chunks with one compare-and-swap
 // on the record's packed (sequence, chunk count, next chunk) word, runs them
@@ -58,9 +61,19 @@ constexpr int kMaxGrid = 2048;        // workgroups per launch (job records)
 constexpr int kOpen = 64;             // board entries
 constexpr int kChunkItems = 1024;     // vertices / survivors per chunk
 constexpr int kChunkQueue = 256;      // queue entries per drain chunk
+constexpr long long kChunkEdges = 1 << 16;  // histogram positions per clearing chunk
 constexpr int kHelpMinDefault = 32768;
 
-enum { PH_INIT = 0, PH_SCAN = 1, PH_DRAIN = 2 };
+enum {
+    PH_INIT = 0, PH_SCAN = 1, PH_DRAIN = 2,                      // PeelOne
+    PH_HZERO = 3, PH_HINIT = 4, PH_HHIST = 5, PH_HFRONT = 6,     // HistoCore set-up
+    PH_HSUM = 7, PH_HUPD = 8, PH_HOUT = 9                        // HistoCore rounds, output
+};
+
+// Items per chunk of each phase (leader and helpers cut phases alike).
+__host__ __device__ inline long long chunk_of(int phase) {
+    return phase == PH_DRAIN || phase == PH_HUPD ? kChunkQueue : phase == PH_HZERO ? kChunkEdges : kChunkItems;
+}
 
 struct alignas(128) JobCtl {
     unsigned long long ctl;   // seq (16) | chunks (24) | next chunk (24); odd seq = open
@@ -116,7 +129,7 @@ struct BatchArgs {
     int algo;
     int lds_cap;       // vertices whose values fit in dynamic LDS
     int sum_wave_min;  // SumHisto: larger values scan with a whole wave
-    int help_min;      // PeelOne graphs of at least this many vertices (global tier) take helpers; 0 = never
+    int help_min;      // graphs of at least this many vertices (global tier) take helpers; 0 = never
     unsigned long long limit;  // bound on every wait (wall-clock ticks)
     BatchState *st;
 };
@@ -493,6 +506,151 @@ __device__ __forceinline__ void g_min(bool pred, int x, int *mn) {
     if (lane_id() == 0 && m != INT_MAX) atomicMin(mn, m);
 }
 
+// One chunk [c0, c1) of a HistoCore phase of graph t (values in t.core, the
+// frontier lists in t.L0 / t.L1 by round parity), run by the whole
+// workgroup; the same steps as histo_graph, with global counters.
+__device__ void run_chunk_histo(const Task &t, const JobParams &p, JobCnt *n, long long c0, long long c1,
+                                ExpandLds &X, Counts &c) {
+    const long long *off = t.off;
+    const long long e0 = t.e0;
+    int32_t *core = t.core;
+    int32_t *histo = t.histo;
+    if (p.phase == PH_HZERO) {  // histogram positions [c0, c1)
+        for (long long e = c0 + threadIdx.x; e < c1; e += kBlock) histo[e] = 0;
+    } else if (p.phase == PH_HINIT) {
+        for (long long i = c0 + threadIdx.x; i < c1; i += kBlock) core[i] = (int)(off[i + 1] - off[i]);
+    } else if (p.phase == PH_HHIST) {  // InitHisto of vertices [c0, c1)
+        for (long long base = c0; base < c1; base += kBlock) {
+            const long long i = base + threadIdx.x;
+            long long rs = 0;
+            int d = 0;
+            if (i < c1) {
+                rs = off[i];
+                d = (int)(off[i + 1] - rs);
+            }
+            block_expand<kBatchRounds>(
+                d, rs, d, 0, t.cols, X,
+                [&](const bool (&act)[kBatchRounds], const int (&u)[kBatchRounds],
+                    const int (&own)[kBatchRounds]) {
+#pragma unroll
+                    for (int r = 0; r < kBatchRounds; ++r) {
+                        if (!act[r]) continue;
+                        const int dv = X.p0[own[r]];
+                        const int b = min(max(core[u[r]], 1), dv);
+                        atomicAdd(&histo[X.e0[own[r]] - e0 + b - 1], 1);
+                    }
+                });
+        }
+    } else if (p.phase == PH_HFRONT) {  // the first frontier: top bucket below the value
+        for (long long i = c0 + threadIdx.x; i - (long long)threadIdx.x < c1; i += kBlock) {
+            bool push = false;
+            if (i < c1) {
+                const int d = core[i];
+                push = d > 0 && histo[off[i] - e0 + d - 1] < d;
+            }
+            g_append(push, (int)i, t.L0, &n->a);
+        }
+    } else if (p.phase == PH_HSUM) {  // SumHisto of frontier entries [c0, c1); p.k: wave threshold
+        const int32_t *Fc = p.cur ? t.L1 : t.L0;
+        const int sum_wave_min = p.k;
+        for (long long base = c0; base < c1; base += kBlock) {
+            const long long i = base + threadIdx.x;
+            int v = -1, c_old = 0;
+            long long rs = 0;
+            if (i < c1) {
+                v = Fc[i];
+                c_old = core[v];
+                rs = off[v] - e0;
+            }
+            if (v >= 0 && c_old <= sum_wave_min) {
+                int sum = 0, kk = c_old;
+                for (; kk >= 1; --kk) {
+                    sum += histo[rs + kk - 1];
+                    if (sum >= kk) break;
+                }
+                if (kk < 1) kk = 0;
+                c.buckets += c_old - max(kk, 1) + 1;
+                core[v] = kk;
+                t.oldcore[v] = c_old;
+                if (kk >= 1) histo[rs + kk - 1] = sum;
+            }
+            unsigned long long mm = __ballot(v >= 0 && c_old > sum_wave_min);
+            while (mm) {
+                const int l = __ffsll(mm) - 1;
+                mm &= mm - 1;
+                const int vv = __shfl(v, l), cc = __shfl(c_old, l);
+                const long long ra = __shfl(rs, l);
+                int top = cc, carry = 0, h = 0, sum = 0;
+                while (top >= 1) {
+                    const int bb = top - lane_id();
+                    const int val = bb >= 1 ? histo[ra + bb - 1] : 0;
+                    const int S = carry + wave_incl_scan(val);
+                    const unsigned long long mk = __ballot(bb >= 1 && S >= bb);
+                    if (mk) {
+                        const int l2 = __ffsll(mk) - 1;
+                        h = top - l2;
+                        sum = __shfl(S, l2);
+                        break;
+                    }
+                    carry = __shfl(S, kWave - 1);
+                    top -= kWave;
+                }
+                if (lane_id() == 0) {
+                    c.buckets += cc - max(h, 1) + 1;
+                    core[vv] = h;
+                    t.oldcore[vv] = cc;
+                    if (h >= 1) histo[ra + h - 1] = sum;
+                }
+            }
+        }
+    } else if (p.phase == PH_HUPD) {  // UpdateHisto of frontier entries [c0, c1)
+        const int32_t *Fc = p.cur ? t.L1 : t.L0;
+        int32_t *Fn = p.cur ? t.L0 : t.L1;
+        for (long long base = c0; base < c1; base += kBlock) {
+            const long long i = base + threadIdx.x;
+            int v = -1, c_new = 0, c_old = 0, d = 0;
+            long long rs = 0;
+            if (i < c1) {
+                v = Fc[i];
+                c_new = core[v];
+                c_old = t.oldcore[v];
+                rs = off[v];
+                d = (int)(off[v + 1] - rs);
+            }
+            c.edges += d;
+            block_expand<kBatchRounds>(
+                d, rs, c_new, c_old, t.cols, X,
+                [&](const bool (&act)[kBatchRounds], const int (&u)[kBatchRounds],
+                    const int (&own)[kBatchRounds]) {
+                    int cu[kBatchRounds];
+#pragma unroll
+                    for (int r = 0; r < kBatchRounds; ++r) cu[r] = act[r] ? core[u[r]] : 0;
+                    bool push[kBatchRounds];
+#pragma unroll
+                    for (int r = 0; r < kBatchRounds; ++r) {
+                        push[r] = false;
+                        const int cvv = X.p0[own[r]], ov = X.p1[own[r]];
+                        if (act[r] && cu[r] > cvv && cvv >= 1) {
+                            const long long hb = off[u[r]] - e0 - 1;
+                            if (ov >= cu[r]) {
+                                push[r] = atomicSub(&histo[hb + cu[r]], 1) == cu[r];
+                            } else {
+                                atomicSub(&histo[hb + ov], 1);
+                            }
+                            atomicAdd(&histo[hb + cvv], 1);
+                            ++c.atomics;
+                            c.pushes += push[r] ? 1 : 0;
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < kBatchRounds; ++r) g_append(push[r], u[r], Fn, &n->b);
+                });
+        }
+    } else {  // PH_HOUT
+        for (long long i = c0 + threadIdx.x; i < c1; i += kBlock) t.out[i] = core[i];
+    }
+}
+
 // One chunk [c0, c1) of a phase of graph t, run by the whole workgroup.
 __device__ void run_chunk(const Task &t, const JobParams &p, JobCnt *n, long long c0, long long c1,
                           ExpandLds &X, Counts &c) {
@@ -525,6 +683,8 @@ __device__ void run_chunk(const Task &t, const JobParams &p, JobCnt *n, long lon
             g_append(cv > k, v, dst, &n->b);
             g_min(cv > k, cv, &n->mn);
         }
+    } else if (p.phase >= PH_HZERO) {
+        run_chunk_histo(t, p, n, c0, c1, X, c);
     } else {  // PH_DRAIN: expand queue entries [c0, c1)
         for (long long base = c0; base < c1; base += kBlock) {
             const long long i = base + threadIdx.x;
@@ -651,11 +811,9 @@ __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shar
     __syncthreads();
 }
 
-// PeelOne of a global-tier graph by its leader, phases shared with helpers.
-__device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long task, LeadLds &sh,
-                                  ExpandLds &X, Counts &c) {
-    Job *job = &a.st->jobs[blockIdx.x];
-    // list the job on the board (no helpers if the board is full)
+// The leader lists its job on the board (no helpers if the board is full)
+// and clears the job's counters.  Returns the board slot, or -1.
+__device__ int board_enter(const BatchArgs &a, Job *job, LeadLds &sh) {
     if (threadIdx.x == 0) {
         sh.err = 0;
         sh.chunk = -1;
@@ -673,8 +831,26 @@ __device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long t
     }
     __syncthreads();
     const int slot = (int)sh.chunk;
-    const bool shared = slot >= 0;
     __syncthreads();
+    return slot;
+}
+
+// The leader takes its job off the board and records how the graph went.
+__device__ void board_leave(const BatchArgs &a, int slot, const LeadLds &sh) {
+    if (threadIdx.x == 0) {
+        if (slot >= 0) st_rlx(&a.st->open[slot], 0ull);
+        if (sh.err) atomicAdd(&a.st->stuck.v, 1ull);
+        atomicAdd(&a.st->helped.v, slot >= 0 ? 1ull : 0ull);
+    }
+    __syncthreads();
+}
+
+// PeelOne of a global-tier graph by its leader, phases shared with helpers.
+__device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long task, LeadLds &sh,
+                                  ExpandLds &X, Counts &c) {
+    Job *job = &a.st->jobs[blockIdx.x];
+    const int slot = board_enter(a, job, sh);
+    const bool shared = slot >= 0;
     JobParams p;
     p.task = task;
     p.pad = 0;
@@ -720,12 +896,50 @@ __device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long t
         k += 1;
     }
     c.frontier += peelable;
-    if (threadIdx.x == 0) {
-        if (shared) st_rlx(&a.st->open[slot], 0ull);
-        if (sh.err) atomicAdd(&a.st->stuck.v, 1ull);
-        atomicAdd(&a.st->helped.v, shared ? 1ull : 0ull);
+    board_leave(a, slot, sh);
+}
+
+// HistoCore of a global-tier graph by its leader, phases shared with helpers
+// (the steps of histo_graph; the rounds stay synchronous because SumHisto
+// and UpdateHisto are separate phases).
+__device__ void histo_graph_helped(const BatchArgs &a, const Task &t, long long task, LeadLds &sh,
+                                   ExpandLds &X, Counts &c) {
+    Job *job = &a.st->jobs[blockIdx.x];
+    const int slot = board_enter(a, job, sh);
+    const bool shared = slot >= 0;
+    const long long m = t.off[t.n] - t.e0;
+    JobParams p;
+    p.task = task;
+    p.pad = 0;
+    p.k = a.sum_wave_min;
+    p.cur = 0;
+    p.lo = 0;
+    const int setup[4] = {PH_HZERO, PH_HINIT, PH_HHIST, PH_HFRONT};
+    for (int ph : setup) {
+        p.phase = ph;
+        p.hi = ph == PH_HZERO ? m : t.n;
+        run_phase(a, t, job, shared, p, p.hi, chunk_of(ph), sh, X, c);
+        if (sh.err) break;
     }
-    __syncthreads();
+    long long nf = sh.a;
+    int cur = 0;
+    while (nf > 0 && !sh.err) {
+        ++c.levels;
+        c.frontier += nf;
+        p.cur = cur;
+        p.hi = nf;
+        p.phase = PH_HSUM;
+        run_phase(a, t, job, shared, p, nf, chunk_of(PH_HSUM), sh, X, c);
+        if (threadIdx.x == 0) st_rlx(&job->n.b, 0u);
+        p.phase = PH_HUPD;
+        run_phase(a, t, job, shared, p, nf, chunk_of(PH_HUPD), sh, X, c);
+        nf = sh.b;
+        cur ^= 1;
+    }
+    p.phase = PH_HOUT;
+    p.hi = t.n;
+    if (!sh.err) run_phase(a, t, job, shared, p, t.n, chunk_of(PH_HOUT), sh, X, c);
+    board_leave(a, slot, sh);
 }
 
 // A workgroup with no graph left helps open jobs until every graph of the
@@ -775,7 +989,7 @@ __device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
         p.cur = ld_rlx(&job->p.cur);
         p.pad = 0;
         const Task t = a.tasks[p.task];
-        const long long chunk = p.phase == PH_DRAIN ? kChunkQueue : kChunkItems;
+        const long long chunk = chunk_of(p.phase);
         const long long c0 = p.lo + ci * chunk, c1 = c0 + chunk < p.hi ? c0 + chunk : p.hi;
         run_chunk(t, p, &job->n, c0, c1, X, c);
         // every wave's stores and atomics performed before the chunk is counted
@@ -819,14 +1033,17 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
         __syncthreads();
         if (j >= a.T) break;
         const Task t = a.tasks[j];
-        if (a.help_min > 0 && a.algo == PICO_ALGO_PEELONE && t.n > a.lds_cap && t.n >= a.help_min)
+        const bool helped = a.help_min > 0 && t.n > a.lds_cap && t.n >= a.help_min;
+        if (helped && a.algo == PICO_ALGO_PEELONE)
             peel_graph_helped(a, t, j, sh, X, c);
+        else if (helped)
+            histo_graph_helped(a, t, j, sh, X, c);
         else
             decompose(t, a.algo, a.lds_cap, a.sum_wave_min, w, X, c);
         __syncthreads();
         if (threadIdx.x == 0) atomicAdd(&a.st->finished.v, 1ull);
     }
-    if (a.help_min > 0 && a.algo == PICO_ALGO_PEELONE) help(a, sh, X, c);
+    if (a.help_min > 0) help(a, sh, X, c);
     // per-thread counts: atomics, edges, buckets, pushes; per-workgroup
     // (uniform, thread 0's): levels, frontier, lds graphs
     const long long s_atom = wave_sum64(c.atomics), s_edges = wave_sum64(c.edges);
@@ -1009,7 +1226,7 @@ constexpr long long kHelpersPerBig = 32;  // extra workgroups per large task in 
 int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune *tune,
                  BatchState *st, pico_batch_stats *stats, hipStream_t stream, long long want) {
     Launch L;
-    const int help_min = algo == PICO_ALGO_PEELONE ? help_min_of(tune) : 0;
+    const int help_min = help_min_of(tune);
     int rc = launch_config(reinterpret_cast<const void *>(batched_kernel), tune, want, &L);
     if (rc) return rc;
     if (L.blocks > kMaxGrid) L.blocks = kMaxGrid;
@@ -1205,7 +1422,8 @@ size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo) {
 }
 
 int help_min_large(const pico_batch_tune *tune, int algo) {
-    return (algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE ? help_min_of(tune) : 0;
+    (void)algo;  // both algorithms take helpers
+    return help_min_of(tune);
 }
 
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo) {

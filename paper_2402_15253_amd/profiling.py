@@ -72,10 +72,12 @@ def kernel_stats(d: str) -> dict:
 
 def counter_per_dispatch(d: str, counter: str) -> dict:
     """Mean counter value (KiB) per dispatch of each decomposition kernel, and
-    the calibration copy's value ('copy': the last copyBuffer dispatch --
-    bench.py's --copy-calibration copy runs after everything it measures, and
-    input generation may dispatch larger copies before it)."""
-    acc, copy_last = {}, (-1, 0.0)
+    the calibration copy's value ('copy'): the last copyBuffer dispatch of at
+    least a quarter of the largest copy's value.  bench.py's
+    --copy-calibration copy runs after everything it measures; input
+    generation may dispatch larger copies before it, and small copies may
+    follow it."""
+    acc, copies = {}, []
     with open(_find(d, "counter_collection.csv")) as f:
         for row in csv.DictReader(f):
             if row.get("Counter_Name") != counter:
@@ -86,11 +88,10 @@ def counter_per_dispatch(d: str, counter: str) -> dict:
                     s, c = acc.get(k, (0.0, 0))
                     acc[k] = (s + val, c + 1)
             if COPY_KERNEL in name:
-                did = int(row.get("Dispatch_Id") or 0)
-                if did >= copy_last[0]:
-                    copy_last = (did, val)
+                copies.append((int(row.get("Dispatch_Id") or 0), val))
     out = {k: s / c for k, (s, c) in acc.items()}
-    out["copy"] = copy_last[1]
+    big = max((v for _, v in copies), default=0.0)
+    out["copy"] = max((c for c in copies if c[1] >= 0.25 * big), default=(0, 0.0))[1]
     return out
 
 

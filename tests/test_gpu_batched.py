@@ -76,10 +76,21 @@ def test_batched_peelone_with_helpers(batch, lds_bytes):
     """PeelOne graphs above a (here small) vertex count are decomposed by
     their workgroup with idle workgroups claiming chunks of each phase; the
     result is the oracle's either way."""
+    _helped_batch(batch, lds_bytes, "peelone")
+
+
+@pytest.mark.parametrize("lds_bytes", [0, -1])
+def test_batched_histocore_with_helpers(batch, lds_bytes):
+    """The same for HistoCore: set-up, SumHisto and UpdateHisto phases shared
+    out, rounds still synchronous."""
+    _helped_batch(batch, lds_bytes, "histocore")
+
+
+def _helped_batch(batch, lds_bytes, algo):
     want = np.concatenate(_per_graph_oracle(batch))
     d = batch.to("cuda")
     tune = pico.BatchTune(lds_bytes, 0, 0, 1000)
-    got, st = pico.coreness_batched(d, "peelone", tune=tune, with_stats=True)
+    got, st = pico.coreness_batched(d, algo, tune=tune, with_stats=True)
     print(f"helpers lds_bytes={lds_bytes} stats={st}", flush=True)
     assert np.array_equal(got.cpu().numpy(), want)
     assert st["helped_graphs"] > 0
@@ -99,12 +110,13 @@ def test_few_large_graphs_mostly_helped():
     b = gg.pack_pairs(torch.tensor(sizes), torch.cat(srcs), torch.cat(dsts), name="three-large")
     want = np.concatenate([oracle.bz_coreness(p.offsets, p.cols) for p in parts])
     d = b.to("cuda")
-    for help_min in (1000, -1):
-        got, st = pico.coreness_batched(d, "peelone", tune=pico.BatchTune(0, 0, 0, help_min),
-                                        with_stats=True)
-        print(f"help_min={help_min} stats={st}", flush=True)
-        assert np.array_equal(got.cpu().numpy(), want), help_min
-        if help_min > 0:
-            assert st["helped_graphs"] == 3 and st["help_chunks"] > 0
-        else:
-            assert st["helped_graphs"] == 0
+    for algo in ("peelone", "histocore"):
+        for help_min in (1000, -1):
+            got, st = pico.coreness_batched(d, algo, tune=pico.BatchTune(0, 0, 0, help_min),
+                                            with_stats=True)
+            print(f"{algo} help_min={help_min} stats={st}", flush=True)
+            assert np.array_equal(got.cpu().numpy(), want), (algo, help_min)
+            if help_min > 0:
+                assert st["helped_graphs"] == 3 and st["help_chunks"] > 0
+            else:
+                assert st["helped_graphs"] == 0

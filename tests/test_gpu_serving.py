@@ -138,13 +138,14 @@ def test_persistent_queue_server_alone_vs_mix():
     raise AssertionError("persistent queue mode is switched off")
 
 
-def test_helped_tasks_repeatable():
-    """Large PeelOne tasks decomposed with 32 helpers each, next to small
-    ones, repeated: every run equals the single-graph result.  (Helpers count
-    a chunk done only after every wave of the workgroup has its stores and
+@pytest.mark.parametrize("algo", ["peelone", "histocore"])
+def test_helped_tasks_repeatable(algo):
+    """Large tasks decomposed with 32 helpers each, next to small ones,
+    repeated: every run equals the single-graph result.  (Helpers count a
+    chunk done only after every wave of the workgroup has its stores and
     atomics performed.)"""
     b = gg.mixed_batch(6, 150_000, 300_000, seed=91, device="cuda")
-    code = pico.PICO_ALGO_PEELONE
+    code = pico.ALGOS[algo]
     alone, keep, tasks = [], [], []
     for g in range(b.num_graphs):
         x0, x1 = int(b.vptr[g]), int(b.vptr[g + 1])
@@ -152,6 +153,7 @@ def test_helped_tasks_repeatable():
         n, m = x1 - x0, int(off[-1] - off[0])
         e0 = int(off[0])
         alone.append(pico.coreness((off - e0).contiguous(), b.cols[e0:e0 + m], "peelone").cpu().numpy())
+        print(f"case {algo} graph {g} n={n} m={m}", flush=True)
         out = torch.full((n,), -1, dtype=torch.int32, device="cuda")
         s = _scratch(n, m, code)
         keep.append((out, s))
