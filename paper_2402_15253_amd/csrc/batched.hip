@@ -126,7 +126,6 @@ using Task = TaskT<long long>;
 struct BatchArgs {
     const Task *tasks;
     long long T;
-    int algo;
     int lds_cap;       // vertices whose values fit in dynamic LDS
     int sum_wave_min;  // SumHisto: larger values scan with a whole wave
     int help_min;      // graphs of at least this many vertices (global tier) take helpers; 0 = never
@@ -652,8 +651,15 @@ __device__ void run_chunk_histo(const Task &t, const JobParams &p, JobCnt *n, lo
 }
 
 // One chunk [c0, c1) of a phase of graph t, run by the whole workgroup.
+// kAlgo: the launch's algorithm (each its own kernel, so neither carries the
+// other's registers).
+template <int kAlgo>
 __device__ void run_chunk(const Task &t, const JobParams &p, JobCnt *n, long long c0, long long c1,
                           ExpandLds &X, Counts &c) {
+    if constexpr (kAlgo == PICO_ALGO_HISTOCORE) {
+        run_chunk_histo(t, p, n, c0, c1, X, c);
+        return;
+    }
     const long long *off = t.off;
     int32_t *core = t.core;
     const int k = p.k;
@@ -683,8 +689,6 @@ __device__ void run_chunk(const Task &t, const JobParams &p, JobCnt *n, long lon
             g_append(cv > k, v, dst, &n->b);
             g_min(cv > k, cv, &n->mn);
         }
-    } else if (p.phase >= PH_HZERO) {
-        run_chunk_histo(t, p, n, c0, c1, X, c);
     } else {  // PH_DRAIN: expand queue entries [c0, c1)
         for (long long base = c0; base < c1; base += kBlock) {
             const long long i = base + threadIdx.x;
@@ -746,6 +750,7 @@ __device__ __forceinline__ long long claim_chunk(Job *job, unsigned long long x)
 // The leader runs phase p over `items` items in chunks of `chunk`, opening
 // it to helpers when there is more than one chunk and the board took the
 // job.  On return every chunk is done and the job's counters are in `sh`.
+template <int kAlgo>
 __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shared, JobParams p,
                           long long items, long long chunk, LeadLds &sh, ExpandLds &X, Counts &c) {
     const long long nch = (items + chunk - 1) / chunk;
@@ -778,7 +783,7 @@ __device__ void run_phase(const BatchArgs &a, const Task &t, Job *job, bool shar
         __syncthreads();
         if (ci < 0) break;
         const long long c0 = p.lo + ci * chunk, c1 = c0 + chunk < p.hi ? c0 + chunk : p.hi;
-        run_chunk(t, p, &job->n, c0, c1, X, c);
+        run_chunk<kAlgo>(t, p, &job->n, c0, c1, X, c);
         ++own;
     }
     // every wave's stores and atomics performed before the count below (the
@@ -859,7 +864,7 @@ __device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long t
     p.cur = 0;
     p.lo = 0;
     p.hi = t.n;
-    run_phase(a, t, job, shared, p, t.n, kChunkItems, sh, X, c);
+    run_phase<PICO_ALGO_PEELONE>(a, t, job, shared, p, t.n, kChunkItems, sh, X, c);
     const int peelable = (int)sh.a;
     int k = sh.mn, cur = 0, qtail = 0, na = peelable;
     while (qtail < peelable && !sh.err) {
@@ -873,7 +878,7 @@ __device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long t
         p.cur = cur;
         p.lo = 0;
         p.hi = na;
-        run_phase(a, t, job, shared, p, na, kChunkItems, sh, X, c);
+        run_phase<PICO_ALGO_PEELONE>(a, t, job, shared, p, na, kChunkItems, sh, X, c);
         const int hi0 = (int)sh.c;
         na = (int)sh.b;
         cur ^= 1;
@@ -887,7 +892,7 @@ __device__ void peel_graph_helped(const BatchArgs &a, const Task &t, long long t
             p.phase = PH_DRAIN;
             p.lo = lo;
             p.hi = hi;
-            run_phase(a, t, job, shared, p, hi - lo, kChunkQueue, sh, X, c);
+            run_phase<PICO_ALGO_PEELONE>(a, t, job, shared, p, hi - lo, kChunkQueue, sh, X, c);
             lo = hi;
             hi = (int)sh.c;
         }
@@ -918,7 +923,7 @@ __device__ void histo_graph_helped(const BatchArgs &a, const Task &t, long long 
     for (int ph : setup) {
         p.phase = ph;
         p.hi = ph == PH_HZERO ? m : t.n;
-        run_phase(a, t, job, shared, p, p.hi, chunk_of(ph), sh, X, c);
+        run_phase<PICO_ALGO_HISTOCORE>(a, t, job, shared, p, p.hi, chunk_of(ph), sh, X, c);
         if (sh.err) break;
     }
     long long nf = sh.a;
@@ -929,21 +934,22 @@ __device__ void histo_graph_helped(const BatchArgs &a, const Task &t, long long 
         p.cur = cur;
         p.hi = nf;
         p.phase = PH_HSUM;
-        run_phase(a, t, job, shared, p, nf, chunk_of(PH_HSUM), sh, X, c);
+        run_phase<PICO_ALGO_HISTOCORE>(a, t, job, shared, p, nf, chunk_of(PH_HSUM), sh, X, c);
         if (threadIdx.x == 0) st_rlx(&job->n.b, 0u);
         p.phase = PH_HUPD;
-        run_phase(a, t, job, shared, p, nf, chunk_of(PH_HUPD), sh, X, c);
+        run_phase<PICO_ALGO_HISTOCORE>(a, t, job, shared, p, nf, chunk_of(PH_HUPD), sh, X, c);
         nf = sh.b;
         cur ^= 1;
     }
     p.phase = PH_HOUT;
     p.hi = t.n;
-    if (!sh.err) run_phase(a, t, job, shared, p, t.n, chunk_of(PH_HOUT), sh, X, c);
+    if (!sh.err) run_phase<PICO_ALGO_HISTOCORE>(a, t, job, shared, p, t.n, chunk_of(PH_HOUT), sh, X, c);
     board_leave(a, slot, sh);
 }
 
 // A workgroup with no graph left helps open jobs until every graph of the
 // launch is finished.
+template <int kAlgo>
 __device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
     __shared__ long long job_ix;
     const unsigned long long t0 = wall_clock64();
@@ -991,7 +997,7 @@ __device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
         const Task t = a.tasks[p.task];
         const long long chunk = chunk_of(p.phase);
         const long long c0 = p.lo + ci * chunk, c1 = c0 + chunk < p.hi ? c0 + chunk : p.hi;
-        run_chunk(t, p, &job->n, c0, c1, X, c);
+        run_chunk<kAlgo>(t, p, &job->n, c0, c1, X, c);
         // every wave's stores and atomics performed before the chunk is counted
         // (the workgroup barrier does not wait for vector-memory traffic)
         wave_mem_drain();
@@ -1005,13 +1011,13 @@ __device__ void help(const BatchArgs &a, LeadLds &sh, ExpandLds &X, Counts &c) {
 }
 
 // One graph, by the workgroup: LDS tier if its values fit.
-template <typename Off>
-__device__ __forceinline__ void decompose(const TaskT<Off> &t, int algo, int lds_cap, int sum_wave_min,
+template <int kAlgo, typename Off>
+__device__ __forceinline__ void decompose(const TaskT<Off> &t, int lds_cap, int sum_wave_min,
                                           WgCounters &w, ExpandLds &X, Counts &c) {
     if (t.n <= 0) return;
     const bool lds = t.n <= lds_cap;
     c.lds += lds ? 1 : 0;
-    if (algo == PICO_ALGO_PEELONE) {
+    if constexpr (kAlgo == PICO_ALGO_PEELONE) {
         if (lds) peel_graph<true>(t, w, X, c);
         else peel_graph<false>(t, w, X, c);
     } else {
@@ -1020,6 +1026,8 @@ __device__ __forceinline__ void decompose(const TaskT<Off> &t, int algo, int lds
     }
 }
 
+// kAlgo: PICO_ALGO_PEELONE or PICO_ALGO_HISTOCORE, one kernel each.
+template <int kAlgo>
 __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
     __shared__ WgCounters w;
     __shared__ ExpandLds X;
@@ -1034,16 +1042,16 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
         if (j >= a.T) break;
         const Task t = a.tasks[j];
         const bool helped = a.help_min > 0 && t.n > a.lds_cap && t.n >= a.help_min;
-        if (helped && a.algo == PICO_ALGO_PEELONE)
-            peel_graph_helped(a, t, j, sh, X, c);
-        else if (helped)
-            histo_graph_helped(a, t, j, sh, X, c);
-        else
-            decompose(t, a.algo, a.lds_cap, a.sum_wave_min, w, X, c);
+        if (helped) {
+            if constexpr (kAlgo == PICO_ALGO_PEELONE) peel_graph_helped(a, t, j, sh, X, c);
+            else histo_graph_helped(a, t, j, sh, X, c);
+        } else {
+            decompose<kAlgo>(t, a.lds_cap, a.sum_wave_min, w, X, c);
+        }
         __syncthreads();
         if (threadIdx.x == 0) atomicAdd(&a.st->finished.v, 1ull);
     }
-    if (a.help_min > 0) help(a, sh, X, c);
+    if (a.help_min > 0) help<kAlgo>(a, sh, X, c);
     // per-thread counts: atomics, edges, buckets, pushes; per-workgroup
     // (uniform, thread 0's): levels, frontier, lds graphs
     const long long s_atom = wave_sum64(c.atomics), s_edges = wave_sum64(c.edges);
@@ -1227,20 +1235,27 @@ int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune
                  BatchState *st, pico_batch_stats *stats, hipStream_t stream, long long want) {
     Launch L;
     const int help_min = help_min_of(tune);
-    int rc = launch_config(reinterpret_cast<const void *>(batched_kernel), tune, want, &L);
+    const bool hc = algo == PICO_ALGO_HISTOCORE;
+    const void *kernel = hc ? reinterpret_cast<const void *>(batched_kernel<PICO_ALGO_HISTOCORE>)
+                            : reinterpret_cast<const void *>(batched_kernel<PICO_ALGO_PEELONE>);
+    int rc = launch_config(kernel, tune, want, &L);
     if (rc) return rc;
     if (L.blocks > kMaxGrid) L.blocks = kMaxGrid;
     BatchArgs a;
     a.tasks = tasks;
     a.T = T;
-    a.algo = algo;
     a.lds_cap = L.lds_bytes / 4;
     a.sum_wave_min = tune && tune->sum_wave_min > 0 ? tune->sum_wave_min : kSumWaveMinDefault;
     a.help_min = help_min;
     a.limit = wall_ticks(60.0);
     a.st = st;
     int rec = prof_begin("batched_kernel", stream);
-    hipLaunchKernelGGL(batched_kernel, dim3((unsigned)L.blocks), dim3(kBlock), L.lds_bytes, stream, a);
+    if (hc)
+        hipLaunchKernelGGL(batched_kernel<PICO_ALGO_HISTOCORE>, dim3((unsigned)L.blocks), dim3(kBlock),
+                           L.lds_bytes, stream, a);
+    else
+        hipLaunchKernelGGL(batched_kernel<PICO_ALGO_PEELONE>, dim3((unsigned)L.blocks), dim3(kBlock),
+                           L.lds_bytes, stream, a);
     prof_end(rec, stream);
     PICO_LAUNCH_CHECK();
     if (stats) {
