@@ -48,7 +48,7 @@ namespace {
 constexpr int kSmall = 16;     // lane-serial work up to this many items
 constexpr int kLdsCap = 2048;  // InitHisto: LDS histogram per wave up to this degree
 constexpr int kInitCh = 1024;  // InitHisto: edges per heavy piece
-constexpr int kSumWave = 512;  // SumHisto: one wave up to this value, a workgroup above
+constexpr int kSumWave = 4096;  // SumHisto: one wave up to this value, a workgroup above
 
 // Cumulative counters.  FET packs (edges << 31) | slots of the frontier lists.
 enum { FET = 0, H_TAIL, HS_TAIL, N_MOVES, N_EDGES, N_BUCKETS };
@@ -127,6 +127,70 @@ __device__ __forceinline__ void wave_reverse_sum(const int32_t *seg, int top, in
         carry = __shfl(S, kWave - 1);
         top -= kWave;
     }
+    s = carry;
+}
+
+// The same from the top bucket down to bucket 1, for larger values: a first
+// pass of 64 buckets (one per lane; the answer is usually near the top),
+// then passes of 64 * kSumSlice buckets in which each lane loads its own
+// contiguous slice at once.  Running sums only grow as b falls, so sum(b..top)
+// - b rises strictly as b falls: the answer lies in the first slice (from the
+// top) whose lowest bucket already meets the test, and that slice's lane
+// finishes it from the values it holds.
+constexpr int kSumSlice = 8;
+__device__ __forceinline__ void wave_reverse_sum_wide(const int32_t *seg, int top, int &h, int &s) {
+    const int lane = lane_id();
+    int carry = 0;
+    {
+        const int b = top - lane;
+        const int val = b >= 1 ? seg[b - 1] : 0;
+        const int S = wave_incl_scan(val);
+        const unsigned long long mk = __ballot(b >= 1 && S >= b);
+        if (mk) {
+            const int l = __ffsll(mk) - 1;
+            h = top - l;
+            s = __shfl(S, l);
+            return;
+        }
+        carry = __shfl(S, kWave - 1);
+        top -= kWave;
+    }
+    while (top >= 1) {
+        const int hi = top - lane * kSumSlice;  // this lane's slice: hi down to hi - kSumSlice + 1
+        int v[kSumSlice];
+        int ls = 0;
+#pragma unroll
+        for (int j = 0; j < kSumSlice; ++j) {
+            v[j] = hi - j >= 1 ? seg[hi - j - 1] : 0;
+            ls += v[j];
+        }
+        const int S = carry + wave_incl_scan(ls);  // carry + sum(lowest bucket of the slice .. top)
+        const int lo = hi - kSumSlice + 1 < 1 ? 1 : hi - kSumSlice + 1;
+        const unsigned long long mk = __ballot(hi >= 1 && S >= lo);
+        if (mk) {
+            const int l = __ffsll(mk) - 1;
+            int hh = 0, ss = 0;
+            if (lane == l) {
+                int run = S - ls;  // carry + the buckets above this slice
+                bool done = false;
+#pragma unroll
+                for (int j = 0; j < kSumSlice; ++j) {
+                    run += v[j];
+                    if (!done && hi - j >= 1 && run >= hi - j) {
+                        hh = hi - j;
+                        ss = run;
+                        done = true;
+                    }
+                }
+            }
+            h = __shfl(hh, l);
+            s = __shfl(ss, l);
+            return;
+        }
+        carry = __shfl(S, kWave - 1);
+        top -= kWave * kSumSlice;
+    }
+    h = 0;
     s = carry;
 }
 
@@ -297,7 +361,7 @@ __device__ void sum_histo(const HcArgs<Off> &a, const int32_t *F, const long lon
             long long ea = __shfl(e0, l);
             long long ii = __shfl(i, l);
             int h, s;
-            wave_reverse_sum(a.histo + ea, cc, 1, 0, h, s);
+            wave_reverse_sum_wide(a.histo + ea, cc, h, s);
             if (lane == 0) {
                 a.core[vv] = h;
                 a.oldcore[vv] = cc;
@@ -420,16 +484,28 @@ __device__ __forceinline__ void hc_relax(const bool (&act0)[kEbR], const int (&u
     }
 }
 
+// InitHisto's per-wave histograms and UpdateHisto's edge window are used in
+// different phases: one LDS block serves both.
+union HcLds {
+    int hist[kWavesPerBlock][kLdsCap];
+    EbLds eb;
+};
+
+// At most 128 VGPRs, so that four workgroups share a compute unit: the
+// histogram moves are memory-side atomics, and more waves in flight raise
+// their rate (RMAT-26: 891 ms at two workgroups per CU, 792 at three, 769 at
+// four).
 template <typename Off>
-__global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
-    __shared__ int lds_all[kWavesPerBlock][kLdsCap];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void hc_persistent(HcArgs<Off> a) {
+    __shared__ HcLds U;
     __shared__ int part[kBlock];
     __shared__ int first_ok;
     __shared__ int lds_scan[kWavesPerBlock];
     __shared__ long long lds_scan_l[kWavesPerBlock];
     __shared__ unsigned long long lds64[1];
     __shared__ unsigned long long snap[kNumCtr + 1];
-    __shared__ EbLds eb;
+    EbLds &eb = U.eb;
     HcState *st = a.st;
     GridState *gs = &st->g;
     const unsigned nb = gridDim.x;
@@ -453,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void hc_persistent(HcArgs<Off> a) {
     }
     if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[0].v);
-    init_histo<Off>(a, lds_all[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64);
+    init_histo<Off>(a, U.hist[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64);
     if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     const unsigned long long h_end = snap[H_TAIL], hs_end = snap[HS_TAIL];
     init_heavy<Off>(a, 0, h_end, 0);
@@ -745,7 +821,7 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
     a.warm_add = warm_add;
     int blocks = 0;
     int rc = persistent_grid(reinterpret_cast<const void *>(hc_persistent<Off>), kBlock,
-                             tune_int("PICO_HC_BLOCKS_PER_CU", 2), grid_want_histocore(m), &blocks);
+                             tune_int("PICO_HC_BLOCKS_PER_CU", 4), grid_want_histocore(m), &blocks);
     if (rc) return rc;
     PICO_LAUNCH("hc_state_init", hc_state_init, dim3(1), dim3(kBlock), stream, a.st);
     PICO_LAUNCH_CHECK();
