@@ -161,6 +161,33 @@ def _roofline(kname: str, alg_bytes: float, avg_ms: float, config: str = "") -> 
             "achievable_peak_method": "device-to-device copy of 2^30 bytes (read + write counted)"}
 
 
+def random_access_roof(pico, st: dict, n: int, m: int, per_kernel: dict, ops: int = 1 << 28) -> dict:
+    """The persistent kernels' times against what their random accesses
+    alone cost at the rates this GPU reaches (pico_probe_random_access) over
+    arrays of the sizes they touch: the per-vertex value array (4n bytes)
+    and HistoCore's histogram (4m bytes).  PeelOne gathers one neighbour
+    value per adjacency entry and makes one atomic per decrement; HistoCore
+    makes two atomics per histogram move.  `frac` is that cost over the
+    measured launch time (1.0 = the launch does nothing but those accesses at
+    the probe's rate)."""
+    vals = pico.probe_random_access(4 * n, ops)
+    hist = pico.probe_random_access(4 * m, ops)
+    out = {"probe": {"values": vals, "histogram": hist}}
+    if "po_persistent" in per_kernel and "peelone" in st:
+        dec = int(st["peelone"]["atomics"])
+        t = (m / vals["gathers_per_s"] + dec / vals["atomics_per_s"]) * 1e3
+        avg = per_kernel["po_persistent"]["avg_ms"]
+        out["po_persistent"] = {"gathers": m, "atomics": dec, "ms_at_probe_rates": round(t, 3),
+                                "avg_launch_ms": avg, "frac": round(t / avg, 4)}
+    if "hc_persistent" in per_kernel and "histocore" in st:
+        moves = int(st["histocore"]["atomics"])
+        t = 2 * moves / hist["atomics_per_s"] * 1e3
+        avg = per_kernel["hc_persistent"]["avg_ms"]
+        out["hc_persistent"] = {"atomics": 2 * moves, "ms_at_probe_rates": round(t, 3),
+                                "avg_launch_ms": avg, "frac": round(t / avg, 4)}
+    return out
+
+
 def _batch_stats_as_plain(st: dict) -> dict:
     """The batched kernel's counters under the names algorithmic_bytes reads."""
     return {"atomics": st["atomics"], "frontier_total": st["frontier_total"],
@@ -701,6 +728,9 @@ def main():
         kname = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"] * per_kernel[k]["launches"])
         pk = per_kernel[kname]
         roofline = _roofline(kname, pk["alg_bytes"], pk["avg_ms"], args.config)
+    random_access = random_access_roof(pico, st, n, m, per_kernel) if per_kernel else None
+    if random_access:
+        log(f"random-access roof: {json.dumps(random_access)}")
 
     # Ablations of PeelOne (outside the timed region): what the dynamic
     # frontier and the assertion decrement save (Tables IV and V).
@@ -793,6 +823,7 @@ def main():
         "config": {"workload": desc, "n": n, "m": m, "step": " + ".join(algos) + ", one each",
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "random_access": random_access,
         "cpu_baseline": cpu,
         "per_algo_ms": {k: round(v / args.steps, 3) for k, v in per_algo_ms.items()},
         "per_algo_gteps": {k: round(m / (v / args.steps / 1e3) / 1e9, 3)

@@ -443,6 +443,27 @@ PICO_API int pico_profile_enable(int on);
  */
 PICO_API int pico_profile_read(pico_kernel_stat *out, int cap, int *count);
 
+/*
+ * pico_probe_random_access -- a measurement aid beside the method, for
+ * judging the kernels: the rate at which this device performs the two
+ * random-access operations both algorithms are built from (the gather of a
+ * neighbour's value, Alg. 4 and Alg. 6; the decrement or histogram update,
+ * Section III-B and Section IV-B), over an array of the size the kernels
+ * touch, with nothing else running.
+ *   buf, bytes     device array, caller-owned, at least 4 bytes; its contents
+ *                  are overwritten.  Operations go to uniformly random 4-byte
+ *                  words of it.
+ *   ops            operations of each kind, > 0.
+ *   gathers_per_s  host double: random 4-byte loads per second.
+ *   atomics_per_s  host double: random 4-byte device-scope atomic adds
+ *                  (returning the old value) per second.
+ * Enqueues, on `stream`, an untimed and a timed launch of each kind, times
+ * the timed ones with HIP events and waits for them.  Errors: PICO_EINVAL
+ * for a null pointer, bytes < 4 or ops <= 0; PICO_EHIP for HIP failures.
+ */
+PICO_API int pico_probe_random_access(void *buf, size_t bytes, int64_t ops, double *gathers_per_s,
+                                      double *atomics_per_s, void *stream);
+
 /* Static description of a status code. */
 PICO_API const char *pico_status_string(int status);
 

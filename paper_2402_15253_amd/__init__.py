@@ -31,7 +31,7 @@ __all__ = [
     "BatchStats", "largest_first", "Task", "ServerConfig", "Request", "Completion",
     "ServerStatus", "pico_task_scratch_bytes", "pico_tasks_workspace_bytes", "pico_coreness_tasks",
     "Server", "pico_server_create", "pico_server_submit", "pico_server_progress",
-    "pico_server_query", "pico_server_destroy",
+    "pico_server_query", "pico_server_destroy", "pico_probe_random_access", "probe_random_access",
 ]
 
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
@@ -58,7 +58,7 @@ EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update",
                     "pico_coreness_batched", "pico_task_scratch_bytes",
                     "pico_tasks_workspace_bytes", "pico_coreness_tasks", "pico_server_create",
                     "pico_server_submit", "pico_server_progress", "pico_server_query",
-                    "pico_server_destroy")
+                    "pico_server_destroy", "pico_probe_random_access")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpico.so")
@@ -212,6 +212,9 @@ def load_library():
     lib.pico_server_query.restype = i32
     lib.pico_server_destroy.argtypes = [vp]
     lib.pico_server_destroy.restype = i32
+    lib.pico_probe_random_access.argtypes = [vp, ctypes.c_size_t, i64, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double), vp]
+    lib.pico_probe_random_access.restype = i32
     lib.pico_profile_enable.argtypes = [i32]
     lib.pico_profile_enable.restype = i32
     lib.pico_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -440,6 +443,25 @@ def select_algorithm(offsets: torch.Tensor, cols: torch.Tensor, workspace=None, 
     rc, chosen, f = pico_select_algorithm(offsets, cols, n, m, a, workspace, workspace.numel(), stream)
     _check(rc)
     return ALGO_NAMES[chosen], {"h_index": f[0], "sampled": f[1], "in_first_frontier": f[2]}
+
+
+def pico_probe_random_access(buf, nbytes: int, ops: int, stream=None):
+    """C ``pico_probe_random_access``: (status, gathers/s, atomics/s)."""
+    g, a = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = load_library().pico_probe_random_access(_ptr(buf), nbytes, ops, ctypes.byref(g), ctypes.byref(a),
+                                                 _stream(stream))
+    return rc, g.value, a.value
+
+
+def probe_random_access(nbytes: int, ops: int = 1 << 28, device="cuda", stream=None) -> dict:
+    """Random 4-byte gathers and atomic adds per second over a scratch array
+    of ``nbytes`` bytes on ``device`` (allocated here and freed on return)."""
+    words = max(1, int(nbytes) // 4)
+    buf = torch.zeros(words, dtype=torch.int32, device=device)
+    rc, g, a = pico_probe_random_access(buf, words * 4, int(ops), stream)
+    _check(rc)
+    del buf
+    return {"bytes": words * 4, "ops": int(ops), "gathers_per_s": g, "atomics_per_s": a}
 
 
 def pico_coreness_update(csr_offsets, csr_cols, n: int, m: int, algo: int, prev_core, bound_add: int,

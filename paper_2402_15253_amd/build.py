@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpico.so")
-SOURCES = ["api.hip", "peelone.hip", "histocore.hip", "batched.hip", "server.hip", "select.hip"]
+SOURCES = ["api.hip", "peelone.hip", "histocore.hip", "batched.hip", "server.hip", "select.hip", "probe.hip"]
 ARCH = os.environ.get("PICO_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

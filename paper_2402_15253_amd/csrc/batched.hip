@@ -409,21 +409,8 @@ __device__ void histo_graph(const TaskT<Off> &t, int sum_wave_min, WgCounters &w
                 mm &= mm - 1;
                 const int vv = __shfl(v, l), cc = __shfl(c_old, l);
                 const long long ra = __shfl(rs, l);
-                int top = cc, carry = 0, h = 0, s = 0;
-                while (top >= 1) {
-                    const int bb = top - lane_id();
-                    const int val = bb >= 1 ? histo[ra + bb - 1] : 0;
-                    const int S = carry + wave_incl_scan(val);
-                    const unsigned long long mk = __ballot(bb >= 1 && S >= bb);
-                    if (mk) {
-                        const int l2 = __ffsll(mk) - 1;
-                        h = top - l2;
-                        s = __shfl(S, l2);
-                        break;
-                    }
-                    carry = __shfl(S, kWave - 1);
-                    top -= kWave;
-                }
+                int h, s;
+                wave_reverse_sum_wide(histo + ra, cc, h, s);
                 if (lane_id() == 0) {
                     c.buckets += cc - max(h, 1) + 1;
                     cv.set(vv, h);
@@ -579,21 +566,8 @@ __device__ void run_chunk_histo(const Task &t, const JobParams &p, JobCnt *n, lo
                 mm &= mm - 1;
                 const int vv = __shfl(v, l), cc = __shfl(c_old, l);
                 const long long ra = __shfl(rs, l);
-                int top = cc, carry = 0, h = 0, sum = 0;
-                while (top >= 1) {
-                    const int bb = top - lane_id();
-                    const int val = bb >= 1 ? histo[ra + bb - 1] : 0;
-                    const int S = carry + wave_incl_scan(val);
-                    const unsigned long long mk = __ballot(bb >= 1 && S >= bb);
-                    if (mk) {
-                        const int l2 = __ffsll(mk) - 1;
-                        h = top - l2;
-                        sum = __shfl(S, l2);
-                        break;
-                    }
-                    carry = __shfl(S, kWave - 1);
-                    top -= kWave;
-                }
+                int h, sum;
+                wave_reverse_sum_wide(histo + ra, cc, h, sum);
                 if (lane_id() == 0) {
                     c.buckets += cc - max(h, 1) + 1;
                     core[vv] = h;

@@ -68,6 +68,72 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     return x;
 }
 
+// SumHisto's reverse summation (Step II of Fig. 6) by one wave, from bucket
+// `top` of a vertex's histogram `seg` (bucket b at seg[b - 1]) down to bucket
+// 1: the first b with sum(b..top) >= b, and that sum (h = 0 if none).  A first
+// pass of 64 buckets (one per lane; the answer is usually near the top),
+// then passes of 64 * kSumSlice buckets in which each lane loads its own
+// contiguous slice at once.  Running sums only grow as b falls, so sum(b..top)
+// - b rises strictly as b falls: the answer lies in the first slice (from the
+// top) whose lowest bucket already meets the test, and that slice's lane
+// finishes it from the values it holds.
+constexpr int kSumSlice = 8;
+__device__ __forceinline__ void wave_reverse_sum_wide(const int32_t *seg, int top, int &h, int &s) {
+    const int lane = lane_id();
+    int carry = 0;
+    {
+        const int b = top - lane;
+        const int val = b >= 1 ? seg[b - 1] : 0;
+        const int S = wave_incl_scan(val);
+        const unsigned long long mk = __ballot(b >= 1 && S >= b);
+        if (mk) {
+            const int l = __ffsll(mk) - 1;
+            h = top - l;
+            s = __shfl(S, l);
+            return;
+        }
+        carry = __shfl(S, kWave - 1);
+        top -= kWave;
+    }
+    while (top >= 1) {
+        const int hi = top - lane * kSumSlice;  // this lane's slice: hi down to hi - kSumSlice + 1
+        int v[kSumSlice];
+        int ls = 0;
+#pragma unroll
+        for (int j = 0; j < kSumSlice; ++j) {
+            v[j] = hi - j >= 1 ? seg[hi - j - 1] : 0;
+            ls += v[j];
+        }
+        const int S = carry + wave_incl_scan(ls);  // carry + sum(lowest bucket of the slice .. top)
+        const int lo = hi - kSumSlice + 1 < 1 ? 1 : hi - kSumSlice + 1;
+        const unsigned long long mk = __ballot(hi >= 1 && S >= lo);
+        if (mk) {
+            const int l = __ffsll(mk) - 1;
+            int hh = 0, ss = 0;
+            if (lane == l) {
+                int run = S - ls;  // carry + the buckets above this slice
+                bool done = false;
+#pragma unroll
+                for (int j = 0; j < kSumSlice; ++j) {
+                    run += v[j];
+                    if (!done && hi - j >= 1 && run >= hi - j) {
+                        hh = hi - j;
+                        ss = run;
+                        done = true;
+                    }
+                }
+            }
+            h = __shfl(hh, l);
+            s = __shfl(ss, l);
+            return;
+        }
+        carry = __shfl(S, kWave - 1);
+        top -= kWave * kSumSlice;
+    }
+    h = 0;
+    s = carry;
+}
+
 __device__ __forceinline__ int wave_max_int(int x) {
     for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
     return x;

@@ -75,6 +75,9 @@ def test_argument_errors_need_no_device():
     assert pico.pico_coreness(None, None, 0, 0, pico.PICO_ALGO_AUTO, None) == pico.PICO_OK
     assert pico.pico_workspace_bytes(1000, 8000, pico.PICO_ALGO_AUTO) >= max(
         pico.pico_workspace_bytes(1000, 8000, a) for a in (pico.PICO_ALGO_PEELONE, pico.PICO_ALGO_HISTOCORE))
+    # random-access probe: argument checks come before any device call
+    assert pico.pico_probe_random_access(None, 1 << 20, 1000)[0] == pico.PICO_EINVAL
+    assert pico.pico_probe_random_access(None, 0, 1000)[0] == pico.PICO_EINVAL
     # Index2core baselines: grid path only
     for alg in (pico.PICO_ALGO_CNTCORE, pico.PICO_ALGO_NBRCORE):
         assert pico.pico_coreness(None, None, 0, 0, alg | pico.PICO_PATH_WG, None) == pico.PICO_ENOTSUP
