@@ -1,0 +1,55 @@
+"""Host-side arithmetic of bench.py (no GPU): the random-access roofline and
+the algorithmic byte models it reports."""
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+class FakeProbe:
+    """Stands in for the library: fixed rates per array size."""
+
+    def __init__(self, rates):
+        self.rates = rates
+        self.calls = []
+
+    def probe_random_access(self, nbytes, ops):
+        self.calls.append(nbytes)
+        g, a = self.rates[nbytes]
+        return {"bytes": nbytes, "ops": ops, "gathers_per_s": g, "atomics_per_s": a}
+
+
+def test_random_access_roof_arithmetic():
+    n, m = 1000, 8000
+    fake = FakeProbe({4 * n: (80e9, 25e9), 4 * m: (50e9, 20e9)})
+    st = {"peelone": {"atomics": 3000}, "histocore": {"atomics": 5000}}
+    per_kernel = {"po_persistent": {"avg_ms": 0.5}, "hc_persistent": {"avg_ms": 2.0}}
+    r = bench.random_access_roof(fake, st, n, m, per_kernel, ops=1 << 10)
+    assert fake.calls == [4 * n, 4 * m]
+    po = r["po_persistent"]
+    want_po = (m / 80e9 + 3000 / 25e9) * 1e3
+    assert po["gathers"] == m and po["atomics"] == 3000
+    assert abs(po["ms_at_probe_rates"] - round(want_po, 3)) < 1e-9
+    assert abs(po["frac"] - round(want_po / 0.5, 4)) < 1e-9
+    hc = r["hc_persistent"]
+    want_hc = 2 * 5000 / 20e9 * 1e3  # two atomics per histogram move, histogram-sized array
+    assert hc["atomics"] == 10000
+    assert abs(hc["frac"] - round(want_hc / 2.0, 4)) < 1e-9
+
+
+def test_random_access_roof_skips_kernels_not_run():
+    fake = FakeProbe({40: (1e9, 1e9), 400: (1e9, 1e9)})
+    r = bench.random_access_roof(fake, {"peelone": {"atomics": 1}}, 10, 100,
+                                 {"po_persistent": {"avg_ms": 1.0}}, ops=8)
+    assert "hc_persistent" not in r and "po_persistent" in r
+
+
+def test_peelone_byte_model():
+    # n(2W + 20) + 8m + 8A (per vertex: two offsets, init, scan, queue, output;
+    # per entry: column and neighbour value; per decrement: one RMW)
+    n, m, w, a = 100, 600, 4, 250
+    assert bench.algorithmic_bytes("peelone", {"atomics": a}, n, m, w) == n * (2 * w + 20) + 8 * m + 8 * a
