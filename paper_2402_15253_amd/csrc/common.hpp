@@ -448,12 +448,21 @@ __device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
         L.next = a;
     }
     __syncthreads();
+    // Window size: about twice the entries one step of kEbWin edges covers at
+    // the round's mean row length.  A step ends at the window's end, so any
+    // size is correct; with long rows a short window saves most of the loads
+    // (UpdateHisto on RMAT-22 averages about 430 edges per entry).
+    int wcap = kEbEnt;
+    if (q1 > q0 && e_hi > e_lo) {
+        const long long want = 2 * (long long)kEbWin * (q1 - q0) / (e_hi - e_lo) + 32;
+        wcap = want < (long long)kEbEnt ? (int)want : kEbEnt;
+    }
     long long i0 = L.next;
     for (long long s0 = lo; s0 < hi;) {
-        // the window: up to kEbEnt entries from the one holding s0, and the
+        // the window: up to wcap entries from the one holding s0, and the
         // start of the entry after them, which bounds the edges this step
         // may take (every entry holds at least one edge, so it lies past s0)
-        const int w = (int)(q1 - i0 < (long long)kEbEnt ? q1 - i0 : (long long)kEbEnt);
+        const int w = (int)(q1 - i0 < (long long)wcap ? q1 - i0 : (long long)wcap);
         for (int j = threadIdx.x; j <= w; j += kBlock) {
             long long i = i0 + j;
             if (j < w) {
