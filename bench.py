@@ -8,7 +8,7 @@ counting each of the two decompositions (2 |E| per step).  Prints one JSON
 line; details of the run go to stderr.
 
 The graph is generated on the GPU from a counter-based RNG before timing.
-``--gpus`` above 1 is refused: this build runs on a single GPU.
+``--gpus`` above 1 is refused: the measurement covers a single GPU.
 """
 from __future__ import annotations
 
@@ -651,7 +651,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+        print("bench.py measures one GPU; runs on several GPUs are not implemented "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
         sys.exit(2)
 

@@ -130,7 +130,7 @@ def test_server_rejects_what_never_fits(pool):
 
 @pytest.mark.skip(reason="persistent request-queue kernel (a kernel polling a request ring in pinned "
                          "host memory and writing completion words there) faulted the GPU twice "
-                         "on its first requests; switched off, see DESIGN.md")
+                         "on its first requests; switched off (the server uses launch slots)")
 def test_persistent_queue_server_alone_vs_mix():
     """Placeholder for the persistent-queue form of the server: the same
     alone-versus-mix check as test_server_alone_vs_mix, with one kernel
