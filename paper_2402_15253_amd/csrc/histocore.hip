@@ -265,9 +265,13 @@ __device__ void sum_histo(const HcArgs<Off> &a, const int32_t *F, const long lon
     GridState *gs = &a.st->g;
     const int lane = lane_id();
     const long long nw = (long long)gridDim.x * kWavesPerBlock;
-    for (long long base = wave_id_global() * kWave; base < nf; base += nw * kWave) {
+    // Entries per wave per step: 64, or fewer when the frontier would leave
+    // waves idle, so that the values a wave scans one after another (below)
+    // are spread over every wave of the grid.
+    const int per = nf >= nw * kWave ? kWave : (int)((nf + nw - 1) / nw);
+    for (long long base = wave_id_global() * per; base < nf; base += nw * per) {
         long long i = base + lane;
-        bool valid = i < nf;
+        bool valid = lane < per && i < nf;
         int v = 0, c_old = 0;
         long long e0 = 0;
         if (valid) {
