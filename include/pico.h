@@ -444,12 +444,12 @@ PICO_API int pico_profile_enable(int on);
 PICO_API int pico_profile_read(pico_kernel_stat *out, int cap, int *count);
 
 /*
- * pico_probe_random_access -- a measurement aid beside the method, for
- * judging the kernels: the rate at which this device performs the two
- * random-access operations both algorithms are built from (the gather of a
- * neighbour's value, Alg. 4 and Alg. 6; the decrement or histogram update,
- * Section III-B and Section IV-B), over an array of the size the kernels
- * touch, with nothing else running.
+ * pico_probe_random_access -- a measurement aid beside the method, against
+ * which the kernels' times can be set: the rate at which this device
+ * performs the two random-access operations both algorithms are built from
+ * (the gather of a neighbour's value, Alg. 4 and Alg. 6; the decrement or
+ * histogram update, Section III-B and Section IV-B), over an array of the
+ * size the kernels touch, with nothing else running.
  *   buf, bytes     device array, caller-owned, at least 4 bytes; its contents
  *                  are overwritten.  Operations go to uniformly random 4-byte
  *                  words of it.
