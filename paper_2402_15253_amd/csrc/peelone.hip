@@ -43,7 +43,7 @@
 // entry's slot through one packed counter, so a round hands every workgroup
 // an equal slice of the round's edges however skewed the degrees are (the
 // load balancing the paper takes from Tigr, Section V-A).  Every thread keeps
-// four edges in flight to hide memory latency.
+// eight edges in flight to hide memory latency.
 //
 // Every vertex enters a frontier exactly once over the whole run, so the
 // global list needs at most n entries.
