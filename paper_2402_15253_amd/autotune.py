@@ -27,6 +27,7 @@ import torch
 
 from . import (ALGOS, BatchStats, BatchTune, PicoError, PICO_OK, pico_batched_workspace_bytes,
                pico_coreness_batched, pico_last_error)
+from .profiling import source_hash
 
 CACHE = os.environ.get("PICO_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "pico", "batched_tune.json"))
@@ -42,7 +43,9 @@ def _key(batch, algo: str) -> str:
     # shape class: graph count and mean sizes to two significant digits
     def sig(x):
         return f"{float(x):.2g}"
-    return f"{p.name}|{p.multi_processor_count}|{algo}|G{sig(G)}|n{sig(n / max(G, 1))}|m{sig(m / max(G, 1))}"
+    # the kernel's sources too: a choice timed on another revision is not reused
+    return (f"{p.name}|{p.multi_processor_count}|{algo}|G{sig(G)}|n{sig(n / max(G, 1))}"
+            f"|m{sig(m / max(G, 1))}|{source_hash('batched_kernel')}")
 
 
 def _load() -> dict:

@@ -53,3 +53,23 @@ def test_peelone_byte_model():
     # per entry: column and neighbour value; per decrement: one RMW)
     n, m, w, a = 100, 600, 4, 250
     assert bench.algorithmic_bytes("peelone", {"atomics": a}, n, m, w) == n * (2 * w + 20) + 8 * m + 8 * a
+
+
+def test_autotune_key_names_kernel_revision(monkeypatch):
+    """The batched autotuner's cache key carries the kernel's source hash, so
+    a choice timed on another revision of the kernel is not reused."""
+    import types
+
+    import torch
+
+    import paper_2402_15253_amd.autotune as at
+    from paper_2402_15253_amd.profiling import source_hash
+
+    props = types.SimpleNamespace(name="gfx950", multi_processor_count=256)
+    monkeypatch.setattr(torch.cuda, "get_device_properties", lambda dev: props)
+    batch = types.SimpleNamespace(offsets=torch.zeros(101, dtype=torch.int64),
+                                  cols=torch.zeros(800, dtype=torch.int32),
+                                  vptr=torch.zeros(5, dtype=torch.int64))
+    key = at._key(batch, "peelone")
+    assert key.startswith("gfx950|256|peelone|G4|n25|m2e+02|")
+    assert key.endswith(source_hash("batched_kernel"))
