@@ -100,8 +100,11 @@ enum {
      *     atomic add; stats.atomics counts both.
      *   PICO_PO_GPP: General Parallel Peel (Alg. 3, Section II-C), the
      *     GPP baseline of Section V -- no dynamic frontier, every neighbour not yet
-     *     removed decremented, k from 1 advancing by one when a scan finds
-     *     nobody; stats.iterations counts every scan. */
+     *     removed decremented, k advancing by one when no residual vertex is
+     *     at or below it; stats.iterations counts Alg. 3's while-loop
+     *     iterations (k is raised at the head of an iteration and scanned
+     *     with in the same one; isolated vertices take the first, at k = 0),
+     *     stats.scans every scan the kernel ran. */
     PICO_PO_STATIC = 0x800,
     PICO_PO_ROLLBACK = 0x1000,
     PICO_PO_GPP = 0x2000

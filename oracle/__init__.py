@@ -165,9 +165,11 @@ def index2core(offsets, cols, variant: str):
 
 def peel_gpp(offsets, cols):
     """General Parallel Peel (Alg. 3, Section II-C), serially: returns
-    (coreness, iterations, decrements), every scan an iteration (k from 1, +1
-    after a scan that finds nobody), one decrement per edge from a removed
-    vertex to a residual one."""
+    (coreness, iterations, decrements).  k starts at 0 with every vertex
+    residual; each while-loop iteration raises k by one when no residual
+    vertex has degree <= k, then scans (possibly finding nobody) and
+    scatters.  One decrement per edge from a removed vertex to a residual
+    one."""
     off, adj = _csr_np(offsets, cols)
     n = off.shape[0] - 1
     x = np.zeros(max(n, 0), dtype=np.int32)

@@ -16,7 +16,8 @@
  *                          Section I: core(v) = the largest k such that v lies
  *                          in the k-core, the maximal subgraph of minimum
  *                          degree >= k.
- *  - oracle_peel_gpp:      General Parallel Peel, serially, counting scans.
+ *  - oracle_peel_gpp:      General Parallel Peel (Alg. 3), serially, counting
+ *                          its while-loop iterations.
  *  - oracle_index2core:    CntCore (Alg. 5) and NbrCore, synchronous rounds,
  *                          with their work counts (Table VI's baselines).
  *  - oracle_peel_static:   PeelOne without the dynamic frontier (Table IV's
@@ -392,14 +393,15 @@ int oracle_index2core(int64_t n, const int64_t *off, const int32_t *adj, int mod
 
 /*
  * General Parallel Peel (Alg. 3, Section II-C; the GPP baseline of Section V),
- * serially: k starts at 1 (isolated vertices have coreness 0); each
- * iteration scans the residual vertices for residual degree <= k; if there
- * are none, k advances by one (that scan still counts as an iteration);
- * otherwise they are removed with coreness k and every residual neighbour
- * loses one degree, and the next iteration scans the same k.  Returns the
- * number of iterations (scans), -1 on bad arguments, -2 on allocation
- * failure; *decrements gets the number of degree decrements (one per edge
- * from a removed vertex to a residual one).
+ * serially, in the algorithm's own order.  k starts at 0 and every vertex,
+ * isolated ones included, starts residual.  Each iteration of the while loop
+ * first raises k by one if no residual vertex has residual degree <= k, then
+ * scans: the residual vertices of degree <= k (which may be none, when even
+ * the raised k finds nobody) are removed with coreness k, and every residual
+ * neighbour of a removed vertex loses one degree.  On G1 this takes the three
+ * iterations Section III-A states.  Returns the number of iterations, -1 on
+ * bad arguments, -2 on allocation failure; *decrements gets the number of
+ * degree decrements (one per edge from a removed vertex to a residual one).
  */
 int64_t oracle_peel_gpp(int64_t n, const int64_t *off, const int32_t *adj, int32_t *core_out,
                         int64_t *decrements)
@@ -411,29 +413,31 @@ int64_t oracle_peel_gpp(int64_t n, const int64_t *off, const int32_t *adj, int32
     unsigned char *alive = (unsigned char *)malloc((size_t)n);
     int32_t *frontier = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     if (!deg || !alive || !frontier) { free(deg); free(alive); free(frontier); return -2; }
-    int64_t left = 0;
     for (int64_t v = 0; v < n; ++v) {
         deg[v] = (int32_t)(off[v + 1] - off[v]);
-        alive[v] = deg[v] > 0;
+        alive[v] = 1;
         core_out[v] = 0;
-        left += alive[v];
     }
+    int64_t left = n;
     int64_t iterations = 0;
-    int32_t k = 1;
+    int32_t k = 0;
     while (left > 0) {
         ++iterations;
+        /* the test that precedes the scan: is any residual vertex at or below k? */
+        int any = 0;
+        for (int64_t v = 0; v < n && !any; ++v)
+            if (alive[v] && deg[v] <= k) any = 1;
+        if (!any) ++k;
+        /* scan */
         int64_t nf = 0;
         for (int64_t v = 0; v < n; ++v)
             if (alive[v] && deg[v] <= k) frontier[nf++] = (int32_t)v;
-        if (nf == 0) {
-            ++k;
-            continue;
-        }
         for (int64_t i = 0; i < nf; ++i) {
             alive[frontier[i]] = 0;
             core_out[frontier[i]] = k;
         }
         left -= nf;
+        /* scatter: residual neighbours only (the rem flag of Alg. 3) */
         for (int64_t i = 0; i < nf; ++i) {
             int32_t v = frontier[i];
             for (int64_t e = off[v]; e < off[v + 1]; ++e)

@@ -74,8 +74,15 @@ constexpr int kTile = kBlock * 8;  // scan items per block step
 //   kGpp      -- General Parallel Peel (Alg. 3, Section II-C; the GPP
 //                baseline of Section V): as kStatic, but every neighbour not
 //                yet removed is decremented (the removal flag is the filter,
-//                not the value), and k starts at 1 and advances by one when
-//                a scan finds nobody, each such scan an iteration.
+//                not the value), and k advances by one at a time.  Alg. 3
+//                raises k at the head of a while-loop iteration, when no
+//                residual vertex is at or below k, and scans with the raised
+//                k in the same iteration; here that test is a scan that finds
+//                nobody, so such a scan right after a scan that removed
+//                vertices opens the next iteration instead of being one.
+//                Isolated vertices, removed at k = 0 in Alg. 3's first
+//                iteration, are written at initialisation and counted as
+//                that iteration.
 enum { kDynamic = 0, kStatic = 1, kRollback = 2, kGpp = 3 };
 
 // Cumulative counters of the grid state.  QET packs (edges << 31) | slots of
@@ -88,7 +95,7 @@ struct PoState {
     Line na[3];  // survivors listed by scan j, in slot j % 3
     Line mn[3];  // smallest surviving value seen by scan j
     Line nf[3];  // vertices claimed by scan j
-    Line levels, scans, kmax, rounds, peelable;
+    Line levels, scans, kmax, rounds, peelable, gpp_iters;
     Line phase[kNumPhases];
 };
 
@@ -461,6 +468,11 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     unsigned long long q_end = 0, e_end = 0;  // global list consumed so far
     long long levels = 0, scans = 0, rounds = 0;
     int kmax = 0;
+    // GPP's while-loop iterations (Alg. 3): the isolated vertices' k = 0
+    // iteration, then every scan except an empty one that follows a scan
+    // that removed vertices (that one is the test opening the next iteration)
+    long long gpp_iters = (long long)peelable < a.n ? 1 : 0;
+    bool gpp_prev_removed = false;
 
     for (int j = 1; peelable > 0; ++j) {
         const int32_t *src = (j & 1) ? a.A0 : a.A1;
@@ -480,9 +492,17 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
         const long long nsurv_in = nprev;
         nprev = (long long)ld_rlx(&st->na[j % 3].v);
         if (ld_rlx(&st->nf[j % 3].v) == 0ull) {  // empty level: jump to the smallest value left
+            if (mode == kGpp) {
+                gpp_iters += gpp_prev_removed ? 0 : 1;
+                gpp_prev_removed = false;
+            }
             if (nprev == 0) break;
             c.k = mode == kGpp ? c.k + 1 : (int)ld_rlx(&st->mn[j % 3].v);
             continue;
+        }
+        if (mode == kGpp) {
+            ++gpp_iters;
+            gpp_prev_removed = true;
         }
         unsigned long long q0 = q_end, e0 = e_end;
         unsigned long long q1 = snap[QET] & kSlotMask, e1 = snap[QET] >> kSlotBits;
@@ -524,6 +544,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
         st->kmax.v = (unsigned long long)kmax;
         st->rounds.v = (unsigned long long)rounds;
         st->peelable.v = peelable;
+        st->gpp_iters.v = (unsigned long long)gpp_iters;
     }
 }
 
@@ -616,7 +637,7 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
         return PICO_EHIP;
     }
     if (stats) {
-        stats->iterations = (int64_t)(mode == kGpp ? h->scans.v : h->levels.v);  // GPP: every scan
+        stats->iterations = (int64_t)(mode == kGpp ? h->gpp_iters.v : h->levels.v);  // GPP: Alg. 3's loop
         stats->sub_rounds = (int64_t)h->rounds.v;
         stats->scans = (int64_t)h->scans.v;
         stats->frontier_total = (int64_t)h->peelable.v;

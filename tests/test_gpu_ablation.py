@@ -59,10 +59,11 @@ def test_rollback_matches_oracle(gi):
 
 @pytest.mark.parametrize("gi", range(len(GRAPHS)))
 def test_gpp_matches_serial_schedule(gi):
-    """General Parallel Peel (Alg. 3): same coreness; its scans (k from 1, +1
-    after an empty scan) are fixed by the graph and equal the serial
-    oracle's, and so is its decrement count: every removed vertex decrements
-    each neighbour still residual, one atomic per such edge."""
+    """General Parallel Peel (Alg. 3): same coreness; its while-loop
+    iterations (k raised at the head of an iteration when nobody residual is
+    at or below it) are fixed by the graph and equal the serial oracle's, and
+    so is its decrement count: every removed vertex decrements each neighbour
+    still residual, one atomic per such edge."""
     g = GRAPHS[gi]()
     print(f"case {g.name} n={g.n} m={g.m}", flush=True)
     want, iters, decrements = oracle.peel_gpp(g.offsets, g.cols)

@@ -432,29 +432,46 @@ def test_cntcore_g1(golden_g1):
 
 
 # ---------------------------------------------------------------- General Parallel Peel (Alg. 3)
-# Pins: BZ; closed forms (k starts at 1 and each scan that finds nobody raises
-# k by one and still counts); G1 from Section II-C's narrative of Alg. 3: in
-# the third iteration the degrees of v3 and v5 fall to 1 (below their
-# coreness 2), so they are removed in a fourth.
+# Pins: BZ; closed forms; G1 from Section III-A, which states that GPP needs
+# three iterations on G1 (Alg. 3 raises k before the scan of the same
+# iteration, so the advance from k = 1 to 2 costs no iteration of its own).
 
 def test_gpp_g1_narrative(golden_g1):
     g = gg.g1()
     x, it, dec = oracle.peel_gpp(g.offsets, g.cols)
     assert x.tolist() == [int(c) for c in golden_g1["coreness"]]
-    # 1: v0, v1 (degree 1); 2: nobody at k = 1, k -> 2; 3: v2, v4, lowering v3, v5 to 1; 4: v3, v5
-    assert it == 4
-    # decrements: iteration 1 along v0-v5, v1-v5; iteration 3 along v2-v5, v2-v3, v4-v3,
-    # v4-v5; v3 and v5 go together in iteration 4, so their edge costs nothing
+    # 1: k 0 -> 1, v0 and v1 (degree 1) go; 2: nobody at or below 1, k -> 2, v2 and
+    # v4 go and v3, v5 fall to degree 1 (Section II-C); 3: v3 and v5 go
+    assert it == 3
+    # decrements: iteration 1 along v0-v5, v1-v5; iteration 2 along v2-v5, v2-v3, v4-v3,
+    # v4-v5; v3 and v5 go together in iteration 3, so their edge costs nothing
     assert dec == 6
 
 
 def test_gpp_closed_forms():
+    # path: both ends go in each iteration, the middle vertex of an odd path
+    # alone in the last; K_n and d-regular graphs: k rises by one per iteration
+    # from 0 to the degree, all removed in the last; star: leaves, then the
+    # centre (degree 0 by then) at the same k; isolated vertices only: one
+    # iteration at k = 0
     for g, iters in ((gg.path(51), 26), (gg.complete(12), 11), (gg.cycle(30), 2), (gg.star(40), 2),
-                     (gg.empty_graph(3), 0), (gg.hypercube(4), 4)):
+                     (gg.empty_graph(3), 1), (gg.hypercube(4), 4)):
         x, it, dec = oracle.peel_gpp(g.offsets, g.cols)
         assert np.array_equal(x, oracle.bz_coreness(g.offsets, g.cols)), g.name
         assert it == iters, g.name
         assert dec <= g.m // 2  # at most one decrement per undirected edge
+
+
+def test_gpp_isolated_vertices_take_the_first_iteration():
+    """Alg. 3 starts at k = 0 with every vertex residual: isolated vertices
+    leave in the first iteration with coreness 0, which adds exactly one
+    iteration to the graph without them."""
+    g = gg.path(11)
+    _, it, dec = oracle.peel_gpp(g.offsets, g.cols)
+    off = np.concatenate([g.offsets.numpy().astype(np.int64), np.full(4, g.m, dtype=np.int64)])
+    x2, it2, dec2 = oracle.peel_gpp(off, g.cols.numpy())
+    assert it2 == it + 1 and dec2 == dec
+    assert x2[-4:].tolist() == [0, 0, 0, 0]
 
 
 @pytest.mark.parametrize("seed", range(4))
