@@ -102,6 +102,20 @@ def coreness_properties(offsets, cols, x) -> dict:
     return out
 
 
+def host_cpu() -> str:
+    """The host CPU's model name and logical CPU count, for the baseline's record."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, nproc={os.cpu_count()}"
+
+
 def cpu_baseline(g, budget_s: float):
     import numpy as np
     import oracle
@@ -346,8 +360,7 @@ def bench_batched(args, pico, torch, np):
         props["sample==oracle"] = same
         cpu = {"value": round(done / t_cpu, 2), "unit": "graphs/s", "cores": 1, "kind": "oracle",
                "sample": f"Batagelj-Zaversnik peel, single thread, {done} graphs of the batch in a "
-                         f"seeded random order ({edges} directed edges, {t_cpu:.1f}s); host "
-                         f"nproc={os.cpu_count()}"}
+                         f"seeded random order ({edges} directed edges, {t_cpu:.1f}s); host {host_cpu()}"}
     ok = all(props.values())
     if not ok:
         log(f"PARITY FAILURE: {props}")
@@ -494,7 +507,7 @@ def bench_serving(args, pico, torch, np):
         done_c, t_cpu, edges, _ = oracle_sample(pool, pk.tolist(), args.cpu_budget)
         cpu = {"value": round(done_c / t_cpu, 2), "unit": "graphs/s", "cores": 1, "kind": "oracle",
                "sample": f"Batagelj-Zaversnik peel, single thread, the first {done_c} requests' "
-                         f"graphs ({edges} directed edges, {t_cpu:.1f}s); host nproc={os.cpu_count()}"}
+                         f"graphs ({edges} directed edges, {t_cpu:.1f}s); host {host_cpu()}"}
     rec = {
         "metric": "served graphs/s with p50/p99 latency (arrival to result) vs a serial plain loop",
         "value": served["graphs_per_s"], "unit": "graphs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -619,7 +632,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="rmat22",
+    ap.add_argument("--config", default="rmat26",
                     choices=["er10k", "rmat22", "rmat26", "batched", "serving", "rmat22-update"])
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
@@ -797,9 +810,8 @@ def main():
         want, runs, t_cpu = cpu_baseline(g, args.cpu_budget)
         cpu = {"value": round(m * runs / t_cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
                "kind": "oracle",
-               "sample": f"Batagelj-Zaversnik peel, single thread, whole {args.config} graph, "
-                         f"{runs} run(s), {t_cpu:.1f}s; host {platform.processor() or 'x86_64'} "
-                         f"nproc={os.cpu_count()}"}
+               "sample": f"Batagelj-Zaversnik peel (the oracle), single thread, whole {args.config} "
+                         f"graph ({m} directed entries), {runs} run(s), {t_cpu:.1f}s; host {host_cpu()}"}
     parity = dict(props)
     if want is not None:
         for k in algos:

@@ -31,6 +31,20 @@
  * thread-local detail string from pico_last_error().
  * Thread safety: calls on different streams may run concurrently from
  * different host threads if each uses its own workspace.
+ *
+ * Test and development overrides (environment variables; unset in
+ * production, where the library picks launch shapes itself).  The first
+ * three are read at each call and must be positive integers (anything else
+ * is ignored); PICO_SMALL_MAX_EDGES is read once per process, >= 0:
+ *   PICO_GRID_BLOCKS        workgroups of a grid-wide persistent launch
+ *                           (capped at what is co-resident)
+ *   PICO_PO_BLOCKS_PER_CU   PeelOne workgroups per compute unit (default 1,
+ *                           2 from 2^28 entries)
+ *   PICO_HC_BLOCKS_PER_CU   HistoCore workgroups per compute unit (default 4;
+ *                           CntCore / NbrCore 2)
+ *   PICO_SMALL_MAX_EDGES    entry bound of the one-workgroup path (default
+ *                           2^14; 0 = never)
+ * They change only the launch shape, never the result.
  */
 #ifndef PICO_H
 #define PICO_H
@@ -141,6 +155,27 @@ typedef struct pico_stats {
                                of long rows. */
 } pico_stats;
 
+/* One step of a decomposition's schedule (pico_coreness_schedule): a level
+   of PeelOne or a round of HistoCore.  64 bytes. */
+typedef struct pico_step {
+    int64_t key;        /* PeelOne: the level's k; HistoCore: the round t = 1, 2, ... */
+    int64_t vertices;   /* PeelOne: vertices peeled at level k, found by the level's
+                           scan or asserted by a decrement (= |{v : core(v) = k}|,
+                           Table V); HistoCore: |V_cnt| of round t, the vertices
+                           whose h-index changes in synchronous round t (Theorem 2) */
+    int64_t work;       /* PeelOne: survivor-list entries the level's scan read;
+                           HistoCore: histogram moves of round t (N1 / N3 updates
+                           of UpdateHisto, two atomics each) */
+    int64_t edges;      /* PeelOne: adjacency entries of the level's edge-balanced
+                           rounds (rows expanded from a workgroup's LDS queue are
+                           not counted); HistoCore: sum of the frontier's degrees,
+                           the edge space of round t's UpdateHisto */
+    int64_t rounds;     /* PeelOne: edge-balanced rounds of the level; HistoCore: 1 */
+    int64_t ns;         /* device wall time of the step (timing, not fixed by the graph) */
+    int64_t scan_ns;    /* of which PeelOne's scan / HistoCore's SumHisto */
+    int64_t reserved;   /* 0 */
+} pico_step;
+
 /* Accumulated HIP-event timing of one kernel over profiled calls. */
 typedef struct pico_kernel_stat {
     const char *name;       /* static string owned by the library */
@@ -175,6 +210,28 @@ PICO_API int pico_workspace_bytes(int64_t n, int64_t m, int algo, size_t *bytes)
 PICO_API int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
                      int algo, int32_t *out_core, void *workspace, size_t ws_bytes,
                      pico_stats *stats, void *stream);
+
+/*
+ * pico_coreness_schedule -- as pico_coreness_ws, and also records the run's
+ * schedule: one pico_step per PeelOne level (Alg. 4: levels k with a
+ * non-empty frontier, in order) or per HistoCore round (Alg. 6: the rounds
+ * of SumHisto then UpdateHisto, in order).
+ *   steps      device pico_step[cap], caller-owned; the first min(cap, count)
+ *              records are written, the rest of the array is untouched.
+ *   cap        >= 0 (0: nothing recorded, the count is still returned).
+ *   num_steps  host int64 (may be NULL): the number of steps the run took
+ *              (= stats->iterations).
+ * `algo` is PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE or PICO_ALGO_AUTO (with
+ * PICO_OFFSETS_I64 as needed); the schedule comes from the grid-wide
+ * persistent kernels, which this call always uses (PICO_PATH_WG and the
+ * ablation flags give PICO_EINVAL; PICO_PATH_GRID is accepted).  Other
+ * arguments, the workspace size (pico_workspace_bytes) and errors as
+ * pico_coreness_ws; a NULL `steps` with cap > 0 is PICO_EINVAL.
+ */
+PICO_API int pico_coreness_schedule(const void *csr_offsets, const int32_t *csr_cols, int64_t n,
+                                    int64_t m, int algo, int32_t *out_core, void *workspace,
+                                    size_t ws_bytes, pico_stats *stats, pico_step *steps, int64_t cap,
+                                    int64_t *num_steps, void *stream);
 
 /*
  * pico_coreness_update -- coreness of a graph that changed since a coreness

@@ -32,6 +32,7 @@ __all__ = [
     "ServerStatus", "pico_task_scratch_bytes", "pico_tasks_workspace_bytes", "pico_coreness_tasks",
     "Server", "pico_server_create", "pico_server_submit", "pico_server_progress",
     "pico_server_query", "pico_server_destroy", "pico_probe_random_access", "probe_random_access",
+    "PicoStep", "pico_coreness_schedule", "coreness_schedule",
 ]
 
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
@@ -58,7 +59,7 @@ EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update",
                     "pico_coreness_batched", "pico_task_scratch_bytes",
                     "pico_tasks_workspace_bytes", "pico_coreness_tasks", "pico_server_create",
                     "pico_server_submit", "pico_server_progress", "pico_server_query",
-                    "pico_server_destroy", "pico_probe_random_access")
+                    "pico_server_destroy", "pico_probe_random_access", "pico_coreness_schedule")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpico.so")
@@ -83,6 +84,15 @@ class PicoStats(ctypes.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "phase_ms"}
         d["phase_ms"] = [round(x, 4) for x in self.phase_ms]
         return d
+
+
+class PicoStep(ctypes.Structure):
+    """C ``pico_step``: one PeelOne level or HistoCore round (64 bytes)."""
+    _fields_ = [(f, ctypes.c_int64) for f in ("key", "vertices", "work", "edges", "rounds", "ns",
+                                               "scan_ns", "reserved")]
+
+
+STEP_FIELDS = tuple(f for f, _ in PicoStep._fields_)
 
 
 class BatchTune(ctypes.Structure):
@@ -176,6 +186,10 @@ def load_library():
     lib.pico_coreness_update.argtypes = [vp, vp, i64, i64, i32, vp, ctypes.c_int32, vp, vp,
                                          ctypes.c_size_t, ctypes.POINTER(PicoStats), vp]
     lib.pico_coreness_update.restype = i32
+    lib.pico_coreness_schedule.argtypes = [vp, vp, i64, i64, i32, vp, vp, ctypes.c_size_t,
+                                           ctypes.POINTER(PicoStats), vp, i64, ctypes.POINTER(ctypes.c_int64),
+                                           vp]
+    lib.pico_coreness_schedule.restype = i32
     lib.pico_select_algorithm.argtypes = [vp, vp, i64, i64, i32, vp, ctypes.c_size_t, ctypes.POINTER(i32),
                                           ctypes.POINTER(ctypes.c_int64), vp]
     lib.pico_select_algorithm.restype = i32
@@ -279,6 +293,43 @@ def pico_coreness_ws(csr_offsets, csr_cols, n: int, m: int, algo: int, out_core,
                                 _ptr(workspace), ws_bytes,
                                 ctypes.byref(stats) if stats is not None else None,
                                 _stream(stream))
+
+
+def pico_coreness_schedule(csr_offsets, csr_cols, n: int, m: int, algo: int, out_core, workspace,
+                           ws_bytes: int, stats: PicoStats | None, steps, cap: int, stream=None):
+    """C ``pico_coreness_schedule`` (``steps``: device buffer of cap * 64
+    bytes); returns (status, number of steps the run took)."""
+    count = ctypes.c_int64(0)
+    rc = load_library().pico_coreness_schedule(_ptr(csr_offsets), _ptr(csr_cols), n, m, algo, _ptr(out_core),
+                                               _ptr(workspace), ws_bytes,
+                                               ctypes.byref(stats) if stats is not None else None,
+                                               _ptr(steps), cap, ctypes.byref(count), _stream(stream))
+    return rc, count.value
+
+
+def coreness_schedule(offsets: torch.Tensor, cols: torch.Tensor, algo="peelone", *, cap: int = 1 << 16,
+                      workspace=None, stream=None):
+    """Coreness plus the run's schedule on the grid path: (core, stats,
+    steps), steps an int64 tensor on the host of shape [count, 8] whose
+    columns are STEP_FIELDS (PeelOne: one row per non-empty level; HistoCore:
+    one row per round).  Raises PicoError if the run took more than ``cap``
+    steps."""
+    if cols.dtype != torch.int32:
+        raise TypeError("cols must be int32")
+    n = offsets.numel() - 1
+    m = cols.numel()
+    a = algo_code(algo, offsets)
+    out = torch.empty(max(n, 0), dtype=torch.int32, device=offsets.device)
+    if workspace is None:
+        workspace = workspace_for(n, m, a, offsets.device)
+    steps = torch.zeros((max(cap, 1), len(STEP_FIELDS)), dtype=torch.int64, device=offsets.device)
+    st = PicoStats()
+    rc, count = pico_coreness_schedule(offsets, cols, n, m, a, out, workspace, workspace.numel(), st, steps,
+                                       cap, stream)
+    _check(rc)
+    if count > cap:
+        raise PicoError(PICO_ENOMEM, f"schedule of {count} steps does not fit cap {cap}")
+    return out, st.as_dict(), steps[:count].cpu()
 
 
 def pico_profile_enable(on: bool) -> int:

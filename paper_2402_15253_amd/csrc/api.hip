@@ -212,7 +212,8 @@ int pick_algo(const void *off, const int32_t *cols, int64_t n, int64_t m, int al
 
 int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int algo, int32_t *out,
              void *ws, size_t ws_bytes, pico_stats *st, hipStream_t s, const int32_t *warm = nullptr,
-             int warm_add = 0) {
+             int warm_add = 0, pico_step *sched = nullptr, int64_t sched_cap = 0,
+             int64_t *sched_len = nullptr) {
     const bool i64 = (algo & PICO_OFFSETS_I64) != 0;
     if ((algo & PICO_ALGO_MASK) == PICO_ALGO_AUTO) {
         int chosen = PICO_ALGO_PEELONE;
@@ -241,14 +242,14 @@ int dispatch(const void *off, const int32_t *cols, int64_t n, int64_t m, int alg
     if ((algo & PICO_ALGO_MASK) == PICO_ALGO_PEELONE) {
         const int mode = (algo & PICO_PO_STATIC) ? 1 : (algo & PICO_PO_ROLLBACK) ? 2 : (algo & PICO_PO_GPP) ? 3 : 0;
         return i64 ? run_peelone<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
-                                          ws_bytes, st, s, mode)
+                                          ws_bytes, st, s, mode, sched, sched_cap, sched_len)
                    : run_peelone<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws,
-                                          ws_bytes, st, s, mode);
+                                          ws_bytes, st, s, mode, sched, sched_cap, sched_len);
     }
     return i64 ? run_histocore<int64_t>(static_cast<const int64_t *>(off), cols, n, m, out, ws,
-                                        ws_bytes, st, s, warm, warm_add)
+                                        ws_bytes, st, s, warm, warm_add, sched, sched_cap, sched_len)
                : run_histocore<int32_t>(static_cast<const int32_t *>(off), cols, n, m, out, ws,
-                                        ws_bytes, st, s, warm, warm_add);
+                                        ws_bytes, st, s, warm, warm_add, sched, sched_cap, sched_len);
 }
 
 template <typename Off>
@@ -387,7 +388,8 @@ namespace {
 // degrees.
 int coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,
                 int32_t *out_core, void *workspace, size_t ws_bytes, pico_stats *stats, void *stream,
-                const int32_t *warm, int warm_add) {
+                const int32_t *warm, int warm_add, pico_step *sched = nullptr, int64_t sched_cap = 0,
+                int64_t *sched_len = nullptr) {
     if (stats) memset(stats, 0, sizeof(*stats));
     int rc = check_args(csr_offsets, csr_cols, n, m, algo, out_core);
     if (rc) return rc;
@@ -405,7 +407,7 @@ int coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int
     }
     auto t0 = std::chrono::steady_clock::now();
     rc = dispatch(csr_offsets, csr_cols, n, m, algo, out_core, workspace, ws_bytes, stats,
-                  static_cast<hipStream_t>(stream), warm, warm_add);
+                  static_cast<hipStream_t>(stream), warm, warm_add, sched, sched_cap, sched_len);
     if (rc) {
         g_prof.pending.clear();
         g_prof.used = 0;
@@ -431,6 +433,27 @@ int pico_coreness_ws(const void *csr_offsets, const int32_t *csr_cols, int64_t n
     clear_error();
     return coreness_ws(csr_offsets, csr_cols, n, m, algo, out_core, workspace, ws_bytes, stats, stream,
                        nullptr, 0);
+}
+
+int pico_coreness_schedule(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,
+                           int32_t *out_core, void *workspace, size_t ws_bytes, pico_stats *stats,
+                           pico_step *steps, int64_t cap, int64_t *num_steps, void *stream) {
+    clear_error();
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (num_steps) *num_steps = 0;
+    const int a = algo & PICO_ALGO_MASK;
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) ||
+        (algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64 | PICO_PATH_GRID)) != 0) {
+        set_error("pico_coreness_schedule records PeelOne, HistoCore or AUTO on the grid path (algo 0x%x)",
+                  algo);
+        return PICO_EINVAL;
+    }
+    if (cap < 0 || (cap > 0 && !steps)) {
+        set_error("bad schedule array (cap %lld)", (long long)cap);
+        return PICO_EINVAL;
+    }
+    return coreness_ws(csr_offsets, csr_cols, n, m, algo | PICO_PATH_GRID, out_core, workspace, ws_bytes,
+                       stats, stream, nullptr, 0, cap > 0 ? steps : nullptr, cap, num_steps);
 }
 
 int pico_select_algorithm(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,

@@ -655,9 +655,12 @@ size_t histocore_ws_bytes(int64_t n, int64_t m);
 // mode: 0 = Alg. 4 (assertion, dynamic frontier); 1 = no dynamic frontier;
 // 2 = fetch-and-add rollback decrement; 3 = General Parallel Peel (the
 // paper's comparison variants).
+// sched (optional, device): one record per non-empty level, the first
+// sched_cap of them; *sched_len (optional, host) gets the level count.
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
-                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream, int mode = 0);
+                void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream, int mode = 0,
+                pico_step *sched = nullptr, int64_t sched_cap = 0, int64_t *sched_len = nullptr);
 
 size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo);
 
@@ -707,10 +710,12 @@ int run_index2core(const Off *off, const int32_t *cols, int64_t n, int64_t m, in
 
 // warm (optional): start from these upper bounds of the coreness, plus
 // warm_add, instead of the degrees.
+// sched / sched_cap / sched_len: as run_peelone, one record per round.
 template <typename Off>
 int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out,
                   void *ws, size_t ws_bytes, pico_stats *st, hipStream_t stream,
-                  const int32_t *warm = nullptr, int warm_add = 0);
+                  const int32_t *warm = nullptr, int warm_add = 0, pico_step *sched = nullptr,
+                  int64_t sched_cap = 0, int64_t *sched_len = nullptr);
 
 inline int grid_for(int64_t items_per_block_units, int cap) {
     int64_t g = items_per_block_units;

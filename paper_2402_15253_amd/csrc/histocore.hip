@@ -57,6 +57,7 @@ constexpr int kSnap = 3;  // counters read at barriers: FET, H_TAIL, HS_TAIL
 struct HcState {
     GridState g;
     Line rounds, first_frontier, frontier_total;
+    Line moves_sched;  // histogram moves so far, flushed every round (schedule only)
     Line phase[kNumPhases];
 };
 
@@ -81,6 +82,9 @@ struct HcArgs {
     unsigned long long limit;
     const int32_t *warm;  // upper bounds of the coreness to start from (nullptr: the degrees)
     int warm_add;         // added to every bound
+    pico_step *sched;     // optional per-round schedule record (device), or null
+    long long sched_cap;
+    double ns_per_tick;   // device wall clock period
 };
 
 inline long long pieces_cap(int64_t m) { return m / kInitCh + m / kLdsCap + 64; }
@@ -489,8 +493,12 @@ void hc_persistent(HcArgs<Off> a) {
     unsigned long long e1 = snap[FET] >> kSlotBits;
     const long long first = nf;
     long long rounds = 0, ftotal = 0;
+    long long nmove_flushed = 0;          // this thread's moves already in moves_sched
+    unsigned long long moves_seen = 0;    // block 0: moves_sched at the last record
     for (int r = 0; nf > 0; ++r) {
         const int cur = r & 1, nxt = cur ^ 1;
+        const unsigned long long t_round = timer ? wall_clock64() : 0ull;
+        const long long e_round = (long long)e1;
         ++rounds;
         ftotal += nf;
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(&gs->ctr[FET].v, 0ull);
@@ -501,6 +509,7 @@ void hc_persistent(HcArgs<Off> a) {
         sum_heavy<Off>(a, a.F[cur], a.FR[cur], hs0, snap[HS_TAIL], part, &first_ok);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[3].v);
+        const unsigned long long t_sum = timer ? wall_clock64() : 0ull;
         const unsigned long long fnext = snap[FET] & kSlotMask;  // 0: cleared this round
         nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? (long long)e1 : 0;
         edge_balanced(a.F[cur], a.FE[cur], a.FR[cur], a.P0, a.P1, 0, nf, 0ll, (long long)e1,
@@ -515,8 +524,25 @@ void hc_persistent(HcArgs<Off> a) {
                           }
                           hc_relax<Off>(act, u, cvr, ovr, du, a, nxt, fnext, nmove);
                       });
+        if (a.sched) {  // this round's moves, for the schedule record
+            flush_count(nmove - nmove_flushed, &st->moves_sched.v);
+            nmove_flushed = nmove;
+        }
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         if (timer) clk.lap(&st->phase[4].v);
+        if (timer && a.sched && r < a.sched_cap) {
+            pico_step *sp = a.sched + r;
+            sp->key = r + 1;
+            sp->vertices = nf;
+            const unsigned long long mv = ld_rlx(&st->moves_sched.v);
+            sp->work = (long long)(mv - moves_seen);
+            moves_seen = mv;
+            sp->edges = e_round;
+            sp->rounds = 1;
+            sp->ns = (long long)((double)(wall_clock64() - t_round) * a.ns_per_tick);
+            sp->scan_ns = (long long)((double)(t_sum - t_round) * a.ns_per_tick);
+            sp->reserved = 0;
+        }
         nf = (long long)((snap[FET] & kSlotMask) - fnext);
         e1 = snap[FET] >> kSlotBits;
     }
@@ -725,7 +751,7 @@ size_t histocore_ws_bytes(int64_t n, int64_t m) {
 template <typename Off>
 int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
                   size_t ws_bytes, pico_stats *stats, hipStream_t stream, const int32_t *warm,
-                  int warm_add) {
+                  int warm_add, pico_step *sched, int64_t sched_cap, int64_t *sched_len) {
     if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
         set_error("m=%lld too large for the packed frontier counter", (long long)m);
         return PICO_ENOTSUP;
@@ -759,6 +785,9 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
     a.limit = wall_ticks(20.0);
     a.warm = warm;
     a.warm_add = warm_add;
+    a.sched = sched;
+    a.sched_cap = sched ? sched_cap : 0;
+    a.ns_per_tick = 1e9 / (double)wall_ticks(1.0);
     int blocks = 0;
     int rc = persistent_grid(reinterpret_cast<const void *>(hc_persistent<Off>), kBlock,
                              tune_int("PICO_HC_BLOCKS_PER_CU", 4), grid_want_histocore(m), &blocks);
@@ -779,6 +808,7 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
                   (unsigned long long)h->g.error.v, blocks);
         return PICO_EHIP;
     }
+    if (sched_len) *sched_len = (int64_t)h->rounds.v;
     if (stats) {
         stats->iterations = (int64_t)h->rounds.v;
         stats->sub_rounds = (int64_t)h->rounds.v;
@@ -796,9 +826,11 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
 }
 
 template int run_histocore<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                    void *, size_t, pico_stats *, hipStream_t, const int32_t *, int);
+                                    void *, size_t, pico_stats *, hipStream_t, const int32_t *, int,
+                                    pico_step *, int64_t, int64_t *);
 template int run_histocore<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                    void *, size_t, pico_stats *, hipStream_t, const int32_t *, int);
+                                    void *, size_t, pico_stats *, hipStream_t, const int32_t *, int,
+                                    pico_step *, int64_t, int64_t *);
 
 size_t index2core_ws_bytes(int64_t n, int64_t m) {
     return histocore_ws_bytes(n, m) + carve_bytes(n, 4) * 4 + carve_bytes(n, 8) * 4;
@@ -836,6 +868,9 @@ int run_index2core(const Off *off, const int32_t *cols, int64_t n, int64_t m, in
     h.limit = wall_ticks(20.0);
     h.warm = nullptr;
     h.warm_add = 0;
+    h.sched = nullptr;
+    h.sched_cap = 0;
+    h.ns_per_tick = 0.0;
     a.cnt = cv.take<int32_t>(n);
     a.mark = cv.take<int32_t>(n);
     for (int b = 0; b < 2; ++b) {

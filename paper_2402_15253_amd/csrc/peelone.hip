@@ -48,9 +48,6 @@
 // Every vertex enters a frontier exactly once over the whole run, so the
 // global list needs at most n entries.
 #include <climits>
-#include <cstdio>
-#include <cstdlib>
-#include <vector>
 
 #include "common.hpp"
 
@@ -95,6 +92,7 @@ struct PoState {
     Line na[3];  // survivors listed by scan j, in slot j % 3
     Line mn[3];  // smallest surviving value seen by scan j
     Line nf[3];  // vertices claimed by scan j
+    Line dynl[3];  // vertices asserted by decrements in the level of scan j (schedule only)
     Line levels, scans, kmax, rounds, peelable, gpp_iters;
     Line phase[kNumPhases];
 };
@@ -113,8 +111,9 @@ struct PoArgs {
     long long *QR;   // ... first CSR position of each entry's row
     PoState *st;
     unsigned long long limit;  // wall-clock ticks any single wait may last
-    long long *trace;          // optional per-level record (development aid), or null
-    int trace_cap;
+    pico_step *sched;          // optional per-level schedule record (device), or null
+    long long sched_cap;
+    double ns_per_tick;        // device wall clock period
     int mode;                  // kDynamic, or an ablation: kStatic, kRollback
 };
 
@@ -473,19 +472,31 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     // that removed vertices (that one is the test opening the next iteration)
     long long gpp_iters = (long long)peelable < a.n ? 1 : 0;
     bool gpp_prev_removed = false;
+    // Schedule record: the vertices the decrements assert during the level
+    // of scan j are added to dynl[j % 3] before each of the level's barriers.
+    int ndyn_flushed = 0;
+    auto flush_dyn = [&](int slot) {
+        if (!a.sched) return;
+        const long long t = wave_sum64(c.ndyn - ndyn_flushed);
+        ndyn_flushed = c.ndyn;
+        if (lane_id() == 0 && t) atomicAdd(&st->dynl[slot].v, (unsigned long long)t);
+    };
 
     for (int j = 1; peelable > 0; ++j) {
         const int32_t *src = (j & 1) ? a.A0 : a.A1;
         int32_t *dst = (j & 1) ? a.A1 : a.A0;
+        const unsigned long long t_level = timer ? wall_clock64() : 0ull;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st_rlx(&st->na[(j + 1) % 3].v, 0ull);
             st_rlx(&st->mn[(j + 1) % 3].v, (unsigned long long)INT_MAX);
             st_rlx(&st->nf[(j + 1) % 3].v, 0ull);
+            st_rlx(&st->dynl[(j + 1) % 3].v, 0ull);
         }
         po_scan<Off, kMode>(a, c, src, nprev, dst, &st->na[j % 3].v, &st->mn[j % 3].v, &st->nf[j % 3].v,
                      lds, lds_l, lds64);
         drain_lds<Off, kMode>(a, c, xl);
         ++scans;
+        flush_dyn(j % 3);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
         const unsigned long long t_scan = wall_clock64();
         if (timer) clk.lap(&st->phase[1].v);
@@ -504,11 +515,13 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
             ++gpp_iters;
             gpp_prev_removed = true;
         }
+        const long long rounds_before = rounds;
         unsigned long long q0 = q_end, e0 = e_end;
         unsigned long long q1 = snap[QET] & kSlotMask, e1 = snap[QET] >> kSlotBits;
         while (q0 < q1) {
             po_round<Off, kMode>(a, c, q0, q1, e0, e1, eb, xl);
             ++rounds;
+            flush_dyn(j % 3);
             if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
             q0 = q1;
             e0 = e1;
@@ -516,16 +529,16 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
             e1 = snap[QET] >> kSlotBits;
         }
         if (timer) clk.lap(&st->phase[2].v);
-        if (timer && a.trace && levels < a.trace_cap) {
-            long long *tr = a.trace + levels * 8;
-            tr[0] = c.k;
-            tr[1] = nsurv_in;
-            tr[2] = (long long)ld_rlx(&st->nf[j % 3].v);
-            tr[3] = (long long)(q1 - q_end);
-            tr[4] = (long long)(e1 - e_end);
-            tr[5] = rounds;
-            tr[6] = (long long)t_scan;
-            tr[7] = (long long)wall_clock64();
+        if (timer && a.sched && levels < a.sched_cap) {
+            pico_step *sp = a.sched + levels;
+            sp->key = c.k;
+            sp->vertices = (long long)(ld_rlx(&st->nf[j % 3].v) + ld_rlx(&st->dynl[j % 3].v));
+            sp->work = nsurv_in;
+            sp->edges = (long long)(e1 - e_end);
+            sp->rounds = rounds - rounds_before;
+            sp->ns = (long long)((double)(wall_clock64() - t_level) * a.ns_per_tick);
+            sp->scan_ns = (long long)((double)(t_scan - t_level) * a.ns_per_tick);
+            sp->reserved = 0;
         }
         q_end = q1;
         e_end = e1;
@@ -556,7 +569,8 @@ size_t peelone_ws_bytes(int64_t n, int64_t m) {
 
 template <typename Off>
 int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32_t *out, void *ws,
-                size_t ws_bytes, pico_stats *stats, hipStream_t stream, int mode) {
+                size_t ws_bytes, pico_stats *stats, hipStream_t stream, int mode, pico_step *sched,
+                int64_t sched_cap, int64_t *sched_len) {
     if ((unsigned long long)m >= (1ull << (64 - kSlotBits))) {
         set_error("m=%lld too large for the packed frontier counter", (long long)m);
         return PICO_ENOTSUP;
@@ -580,14 +594,10 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
         return PICO_ENOMEM;
     }
     a.limit = wall_ticks(20.0);
-    a.trace = nullptr;
-    a.trace_cap = 0;
+    a.sched = sched;
+    a.sched_cap = sched ? sched_cap : 0;
+    a.ns_per_tick = 1e9 / (double)wall_ticks(1.0);
     a.mode = mode;
-    const char *trace_file = getenv("PICO_TRACE_FILE");  // development aid
-    if (trace_file && *trace_file) {
-        a.trace_cap = 1 << 14;
-        PICO_HIP_TRY(hipMallocAsync((void **)&a.trace, sizeof(long long) * 8 * a.trace_cap, stream));
-    }
     int blocks = 0;
     // One workgroup per CU keeps the grid barriers cheap, which decides small
     // graphs (RMAT-22: 21.4 ms at one, 23.1 at two); on graphs with billions
@@ -613,29 +623,12 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     if (!h) return PICO_EHIP;
     PICO_HIP_TRY(hipMemcpyAsync(h, a.st, sizeof(PoState), hipMemcpyDeviceToHost, stream));
     PICO_HIP_TRY(hipStreamSynchronize(stream));
-    if (a.trace) {
-        const long long nl = (long long)h->levels.v < a.trace_cap ? (long long)h->levels.v : a.trace_cap;
-        std::vector<long long> tr((size_t)nl * 8 + 1);
-        PICO_HIP_TRY(hipMemcpy(tr.data(), a.trace, sizeof(long long) * 8 * nl, hipMemcpyDeviceToHost));
-        PICO_HIP_TRY(hipFree(a.trace));
-        if (FILE *f = fopen(trace_file, "a")) {
-            const double us = 1.0 / (double)wall_ticks(1e-6);
-            fprintf(f, "# level k survivors_in scan_claimed global_entries global_edges rounds_cum "
-                       "rounds_us total_us\n");
-            for (long long i = 0; i < nl; ++i) {
-                const long long *t = &tr[i * 8];
-                double prev_end = i ? (double)tr[(i - 1) * 8 + 7] : (double)t[6];
-                fprintf(f, "%lld %lld %lld %lld %lld %lld %lld %.1f %.1f\n", i, t[0], t[1], t[2], t[3],
-                        t[4], t[5], (t[7] - t[6]) * us, (t[7] - prev_end) * us);
-            }
-            fclose(f);
-        }
-    }
     if (h->g.error.v) {
         set_error("PeelOne kernel stopped (error %llu; grid of %d blocks)",
                   (unsigned long long)h->g.error.v, blocks);
         return PICO_EHIP;
     }
+    if (sched_len) *sched_len = (int64_t)h->levels.v;
     if (stats) {
         stats->iterations = (int64_t)(mode == kGpp ? h->gpp_iters.v : h->levels.v);  // GPP: Alg. 3's loop
         stats->sub_rounds = (int64_t)h->rounds.v;
@@ -653,8 +646,10 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
 }
 
 template int run_peelone<int32_t>(const int32_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                  void *, size_t, pico_stats *, hipStream_t, int);
+                                  void *, size_t, pico_stats *, hipStream_t, int, pico_step *, int64_t,
+                                  int64_t *);
 template int run_peelone<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int32_t *,
-                                  void *, size_t, pico_stats *, hipStream_t, int);
+                                  void *, size_t, pico_stats *, hipStream_t, int, pico_step *, int64_t,
+                                  int64_t *);
 
 }  // namespace pico

@@ -28,3 +28,8 @@ def read_golden(name):
 @pytest.fixture(scope="session")
 def golden_g1():
     return read_golden("g1.txt")
+
+
+@pytest.fixture(scope="session")
+def golden_rmat22_jacobi():
+    return read_golden("rmat22_jacobi.txt")

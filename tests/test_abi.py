@@ -135,3 +135,19 @@ def test_task_and_server_argument_checks_need_no_device():
     assert pico.pico_server_create(cfg)[0] == pico.PICO_EINVAL
     assert ctypes.sizeof(pico.ServerConfig) == 4 + 4 + 8 + 8 + 8 + 16 + 16 + 4 + 4
     assert pico.pico_server_destroy(None) == pico.PICO_OK
+
+
+def test_schedule_argument_errors_need_no_device():
+    """pico_coreness_schedule: algorithm and path checked before any device
+    work; n == 0 records nothing and reports zero steps."""
+    assert ctypes.sizeof(pico.PicoStep) == 64
+    rc, count = pico.pico_coreness_schedule(None, None, 0, 0, pico.PICO_ALGO_HISTOCORE, None, None, 0, None,
+                                            None, 0)
+    assert (rc, count) == (pico.PICO_OK, 0)
+    for bad in (pico.PICO_PATH_WG, pico.PICO_PO_STATIC, pico.PICO_ALGO_NBRCORE, 0x4000):
+        rc, _ = pico.pico_coreness_schedule(None, None, 0, 0, bad, None, None, 0, None, None, 0)
+        assert rc == pico.PICO_EINVAL, bad
+    rc, _ = pico.pico_coreness_schedule(None, None, 0, 0, 0, None, None, 0, None, None, 4)
+    assert rc == pico.PICO_EINVAL and "schedule" in pico.pico_last_error()
+    rc, _ = pico.pico_coreness_schedule(None, None, 0, 0, 0, None, None, 0, None, None, -1)
+    assert rc == pico.PICO_EINVAL

@@ -13,6 +13,7 @@ import torch
 import graphgen as gg
 import oracle
 import paper_2402_15253_amd as pico
+from tests.golden.make_schedules import fingerprint
 
 pytestmark = pytest.mark.gpu
 
@@ -146,6 +147,116 @@ def test_er10k_both_and_schedules(path):
     assert st_hc["frontier_total"] == sum(per_round)
 
 
+def _schedule(g, algo):
+    """(coreness, stats, steps) of the grid path with the per-step record."""
+    d = _gpu(g)
+    core, st, steps = pico.coreness_schedule(d.offsets, d.cols, algo)
+    torch.cuda.synchronize()
+    return core.cpu().numpy(), st, steps.numpy()
+
+
+def _check_peelone_levels(want, st, steps):
+    """PeelOne's levels are the distinct non-zero coreness values in
+    increasing order, and level k peels exactly {v : core(v) = k} (Alg. 4,
+    Table V: l1 = k_max when no level is empty)."""
+    vals, counts = np.unique(want[want > 0], return_counts=True)
+    assert steps.shape[0] == st["iterations"] == vals.size
+    assert np.array_equal(steps[:, 0], vals), "levels visited differ from the coreness values"
+    assert np.array_equal(steps[:, 1], counts), "vertices peeled per level differ"
+    assert (steps[:, 2] > 0).all() and (steps[:, 4] >= 0).all() and (steps[:, 7] == 0).all()
+
+
+def _check_histocore_rounds(st, steps, per_round):
+    """HistoCore's round-t frontier is the synchronous iteration's round-t
+    changed set (Theorem 2): sizes compared round by round."""
+    assert steps.shape[0] == st["iterations"] == len(per_round)
+    assert np.array_equal(steps[:, 0], np.arange(1, len(per_round) + 1))
+    assert np.array_equal(steps[:, 1], np.asarray(per_round, dtype=np.int64)), \
+        f"frontier sizes {steps[:, 1].tolist()} vs synchronous rounds {list(per_round)}"
+    assert int(steps[:, 3].sum()) == st["edges_scanned"]
+    assert int(steps[:, 2].sum()) == st["atomics"]  # histogram moves, round by round
+    assert (steps[:, 4] == 1).all()
+
+
+@pytest.mark.parametrize("make", [lambda: gg.er_10k(), lambda: gg.rmat(13, 16, 8),
+                                  lambda: gg.scaled_rmat_block(14, 7, 300, 0.6, 40),
+                                  lambda: gg.disjoint_union(gg.complete(30), gg.cycle(50), gg.empty_graph(4))])
+def test_schedule_matches_oracle_per_step(make):
+    """The per-step schedule against the oracle, element by element: PeelOne
+    level by level against BZ's coreness, HistoCore round by round against
+    the synchronous h-index iteration (hindex_jacobi)."""
+    g = make()
+    print(f"case {g.name} n={g.n} m={g.m}", flush=True)
+    want = oracle.bz_coreness(g.offsets, g.cols)
+    core, st, steps = _schedule(g, "peelone")
+    assert np.array_equal(core, want)
+    _check_peelone_levels(want, st, steps)
+    core, st, steps = _schedule(g, "histocore")
+    assert np.array_equal(core, want)
+    _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
+    _check_histocore_rounds(st, steps, per_round)
+
+
+@pytest.mark.parametrize("make", [lambda: gg.er_gnp(1500, 6.0, 4), lambda: gg.rmat(10, 8, 2), lambda: gg.g1()])
+def test_schedule_matches_serial_traces(make):
+    """On small graphs the serial Alg. 4 / Alg. 6 traces give the sets
+    themselves: PeelOne's level k holds the trace's scan plus dynamic
+    frontier of level k; HistoCore's round t has the trace's V_cnt, whose
+    degrees sum to the round's UpdateHisto edge space."""
+    g = make()
+    deg = np.diff(g.offsets.numpy().astype(np.int64))
+    core, st, steps = _schedule(g, "peelone")
+    tr = oracle.peelone_trace(g.offsets, g.cols)
+    lv = [(L["k"], len(L["scan"]) + len(L["dynamic"])) for L in tr["levels"] if L["scan"] or L["dynamic"]]
+    assert [tuple(r) for r in steps[:, :2].tolist()] == lv
+    core, st, steps = _schedule(g, "histocore")
+    ht = oracle.histocore_trace(g.offsets, g.cols)
+    assert steps[:, 1].tolist() == [len(f) for f in ht["frontiers"]]
+    assert steps[:, 3].tolist() == [int(deg[f].sum()) for f in ht["frontiers"]]
+
+
+def test_schedule_rmat22_full_size(golden_rmat22_jacobi):
+    """RMAT-22 at full size: PeelOne's levels against BZ, HistoCore's 29
+    rounds against the synchronous iteration's changed counts stored by
+    tests/golden/make_schedules.py (the same graph, checked by fingerprint)."""
+    gold = golden_rmat22_jacobi
+    g = gg.rmat22(device="cuda")
+    print(f"case {g.name} n={g.n} m={g.m}", flush=True)
+    off_h, cols_h = g.offsets.cpu().numpy(), g.cols.cpu().numpy()
+    assert (g.n, g.m) == (int(gold["n"][0]), int(gold["m"][0]))
+    assert fingerprint(off_h, cols_h) == gold["sha256"][0], "not the graph the stored schedule was taken on"
+    want = oracle.bz_coreness(off_h, cols_h)
+    core, st, steps = pico.coreness_schedule(g.offsets, g.cols, "peelone")
+    assert np.array_equal(core.cpu().numpy(), want)
+    _check_peelone_levels(want, st, steps.numpy())
+    core, st, steps = pico.coreness_schedule(g.offsets, g.cols, "histocore")
+    assert np.array_equal(core.cpu().numpy(), want)
+    _check_histocore_rounds(st, steps.numpy(), [int(x) for x in gold["changed_per_round"]])
+
+
+def test_schedule_cap_and_errors():
+    """A short array gets the first cap records and the full count; cap 0
+    records nothing; the one-workgroup path and the ablations are refused."""
+    g = _gpu(gg.rmat(12, 16, 5))
+    a = pico.algo_code("peelone", g.offsets)
+    ws = pico.workspace_for(g.n, g.m, a, "cuda")
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    full = torch.zeros((4096, 8), dtype=torch.int64, device="cuda")
+    rc, count = pico.pico_coreness_schedule(g.offsets, g.cols, g.n, g.m, a, out, ws, ws.numel(), None, full,
+                                            4096)
+    assert rc == pico.PICO_OK and 3 < count < 4096
+    short = torch.full((3, 8), -9, dtype=torch.int64, device="cuda")
+    rc, count2 = pico.pico_coreness_schedule(g.offsets, g.cols, g.n, g.m, a, out, ws, ws.numel(), None, short, 2)
+    assert rc == pico.PICO_OK and count2 == count
+    s = short.cpu()
+    assert torch.equal(s[:2, :2], full[:2, :2].cpu()) and (s[2] == -9).all()
+    rc, count3 = pico.pico_coreness_schedule(g.offsets, g.cols, g.n, g.m, a, out, ws, ws.numel(), None, None, 0)
+    assert rc == pico.PICO_OK and count3 == count
+    for bad in (a | pico.PICO_PATH_WG, a | pico.PICO_PO_GPP, pico.PICO_ALGO_CNTCORE):
+        rc, _ = pico.pico_coreness_schedule(g.offsets, g.cols, g.n, g.m, bad, out, ws, ws.numel(), None, full, 8)
+        assert rc == pico.PICO_EINVAL
+
+
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("offsets_dtype", [torch.int32, torch.int64])
 def test_rmat_medium(algo, offsets_dtype):
@@ -162,7 +273,10 @@ def test_rmat_block_deep_hierarchy(algo):
 
 
 @pytest.mark.parametrize("path", ["grid", "wg"])
-def test_histocore_round_sizes_match_jacobi(path):
+def test_histocore_rounds_match_jacobi_both_paths(path):
+    """Round count and total frontier on either path (the one-workgroup path
+    keeps no per-round record; the grid path's record is compared round by
+    round in test_schedule_matches_oracle_per_step)."""
     g = gg.rmat(13, 16, 8)
     _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
     _, st = _check(g, "histocore", path)
@@ -223,22 +337,30 @@ def test_rmat22_full_size(algo):
 
 
 def test_rmat26_block_full_size():
-    """The RMAT-26 + planted-block workload at full size (int64 offsets), in the
-    launch configuration bench.py times.  The oracle cannot finish it in test
-    time, so the checks are ones that hold at any size: both algorithms agree
-    bit for bit, 0 <= core <= deg with 0 exactly on isolated vertices, and the
-    h-index fixed point (so every {core >= k} has minimum degree >= k); plus
-    PeelOne's level count equals the number of distinct non-zero values."""
+    """The RMAT-26 + planted-block workload at full size (int64 offsets, m >
+    2^31), in the launch configuration bench.py times: both algorithms
+    against the oracle (BZ on the host over the whole graph) on every vertex;
+    PeelOne's level count and k_max against the oracle's coreness; the
+    properties that hold at any size as an extra."""
     import bench
     g = gg.rmat26_block(device="cuda")
     print(f"case {g.name} n={g.n} m={g.m}", flush=True)
-    assert g.offsets.dtype == torch.int64
+    assert g.offsets.dtype == torch.int64 and g.m >= 2 ** 31
     po, st_po = pico.coreness(g.offsets, g.cols, "peelone", with_stats=True)
     hc, st_hc = pico.coreness(g.offsets, g.cols, "histocore", with_stats=True)
-    assert torch.equal(po, hc)
     props = bench.coreness_properties(g.offsets, g.cols, po)
     assert all(props.values()), props
-    vals = torch.unique(po)
-    assert st_po["iterations"] == int((vals > 0).sum())
-    assert st_po["k_max"] == int(vals.max())
-    assert st_po["frontier_total"] == int((po > 0).sum())
+    po, hc = po.cpu().numpy(), hc.cpu().numpy()
+    off_h = g.offsets.cpu().numpy()
+    cols_h = g.cols.cpu().numpy()
+    del g
+    torch.cuda.empty_cache()
+    print("oracle: BZ over the whole graph", flush=True)
+    want = oracle.bz_coreness(off_h, cols_h)
+    for name, got in (("peelone", po), ("histocore", hc)):
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, f"{name}: {bad.size} vertices differ from the oracle, first {bad[:5]}"
+    vals = np.unique(want[want > 0])
+    assert st_po["iterations"] == vals.size
+    assert st_po["k_max"] == int(want.max())
+    assert st_po["frontier_total"] == int((want > 0).sum())
