@@ -56,14 +56,19 @@ def algorithmic_bytes(algo: str, st: dict, n: int, m: int, w: int) -> float:
     writes, core and oldcore re-read, two offsets (28 + 2w + 4 b_v); per
     adjacency entry scanned by UpdateHisto the column and core[u] (8); per
     histogram move two atomic read-modify-writes (16); per push a queue
-    write (4).  Plus the output (4n).
+    write (4).  A round that rebuilds the histograms instead of UpdateHisto
+    (stats "scans" counts them; each adds m to edges_scanned) moves what
+    InitHisto does from the current values: two offsets and core[v] per
+    vertex (2w + 4), column, core[u] and a bucket write per entry (12).
+    Plus the output (4n).
     """
     if algo == "peelone":
         return n * (2 * w + 20) + 8 * m + 8 * st["atomics"]
     F, P = st["frontier_total"], st["pushes_dynamic"]
+    R = st.get("scans", 0)
     init = n * (2 * w + 8) + 12 * m + 4 * (F - P)
-    rounds = (F * (28 + 2 * w) + 4 * st["buckets_scanned"] + 8 * st["edges_scanned"]
-              + 16 * st["atomics"] + 4 * P)
+    rounds = (F * (28 + 2 * w) + 4 * st["buckets_scanned"] + 8 * (st["edges_scanned"] - R * m)
+              + 16 * st["atomics"] + 4 * P + R * (n * (2 * w + 4) + 12 * m))
     return init + rounds + 4 * n
 
 

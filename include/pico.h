@@ -33,8 +33,8 @@
  * different host threads if each uses its own workspace.
  *
  * Test and development overrides (environment variables; unset in
- * production, where the library picks launch shapes itself).  The first
- * three are read at each call and must be positive integers (anything else
+ * production, where the library picks launch shapes itself).  All but the
+ * last are read at each call and must be positive integers (anything else
  * is ignored); PICO_SMALL_MAX_EDGES is read once per process, >= 0:
  *   PICO_GRID_BLOCKS        workgroups of a grid-wide persistent launch
  *                           (capped at what is co-resident)
@@ -42,9 +42,13 @@
  *                           2 from 2^28 entries)
  *   PICO_HC_BLOCKS_PER_CU   HistoCore workgroups per compute unit (default 4;
  *                           CntCore / NbrCore 2)
+ *   PICO_HC_REBUILD_PERMILLE HistoCore rounds whose frontier rows hold at least
+ *                           this share of the m entries (in 1/1000; default
+ *                           700, above 1000 never) rebuild the histograms
+ *                           instead of running UpdateHisto
  *   PICO_SMALL_MAX_EDGES    entry bound of the one-workgroup path (default
  *                           2^14; 0 = never)
- * They change only the launch shape, never the result.
+ * They change only the launch shape or the work, never the result.
  */
 #ifndef PICO_H
 #define PICO_H
@@ -173,7 +177,9 @@ typedef struct pico_step {
     int64_t rounds;     /* PeelOne: edge-balanced rounds of the level; HistoCore: 1 */
     int64_t ns;         /* device wall time of the step (timing, not fixed by the graph) */
     int64_t scan_ns;    /* of which PeelOne's scan / HistoCore's SumHisto */
-    int64_t reserved;   /* 0 */
+    int64_t kind;       /* HistoCore: 0 = UpdateHisto round, 1 = round that rebuilt
+                           every histogram from the current values instead (same
+                           histograms and next frontier); PeelOne: 0 */
 } pico_step;
 
 /* Accumulated HIP-event timing of one kernel over profiled calls. */

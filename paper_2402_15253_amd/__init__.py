@@ -89,7 +89,7 @@ class PicoStats(ctypes.Structure):
 class PicoStep(ctypes.Structure):
     """C ``pico_step``: one PeelOne level or HistoCore round (64 bytes)."""
     _fields_ = [(f, ctypes.c_int64) for f in ("key", "vertices", "work", "edges", "rounds", "ns",
-                                               "scan_ns", "reserved")]
+                                               "scan_ns", "kind")]
 
 
 STEP_FIELDS = tuple(f for f, _ in PicoStep._fields_)

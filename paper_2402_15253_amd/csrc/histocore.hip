@@ -49,6 +49,14 @@ constexpr int kSmall = 16;     // lane-serial work up to this many items
 constexpr int kLdsCap = 2048;  // InitHisto: LDS histogram per wave up to this degree
 constexpr int kInitCh = 1024;  // InitHisto: edges per heavy piece
 constexpr int kSumWave = 4096;  // SumHisto: one wave up to this value, a workgroup above
+// Rounds whose frontier rows hold at least this share of m (in 1/1000)
+// rebuild the histograms instead of running UpdateHisto.  Measured on
+// MI355X: a rebuild costs about one InitHisto pass (RMAT-26: 50 ms, RMAT-22:
+// 2.9 ms), an UpdateHisto round about 115 ps per histogram move, and moves
+// run at 0.25-0.47 of a round's frontier edges; rebuilding paid in the
+// rounds whose frontier rows held at least 0.7 of the entries (the first
+// five on both graphs) and lost in the next ones.
+constexpr int kRebuildPermille = 700;
 
 // Cumulative counters.  FET packs (edges << 31) | slots of the frontier lists.
 enum { FET = 0, H_TAIL, HS_TAIL, N_MOVES, N_EDGES, N_BUCKETS };
@@ -58,6 +66,7 @@ struct HcState {
     GridState g;
     Line rounds, first_frontier, frontier_total;
     Line moves_sched;  // histogram moves so far, flushed every round (schedule only)
+    Line rebuilds;     // rounds that rebuilt the histograms instead of UpdateHisto
     Line phase[kNumPhases];
 };
 
@@ -80,8 +89,11 @@ struct HcArgs {
     long long hcap;
     HcState *st;
     unsigned long long limit;
+    long long m;
     const int32_t *warm;  // upper bounds of the coreness to start from (nullptr: the degrees)
     int warm_add;         // added to every bound
+    int rebuild_permille; // a round whose frontier rows hold >= this share of m (in 1/1000)
+                          // rebuilds the histograms instead of UpdateHisto
     pico_step *sched;     // optional per-round schedule record (device), or null
     long long sched_cap;
     double ns_per_tick;   // device wall clock period
@@ -136,9 +148,14 @@ __device__ __forceinline__ void wave_reverse_sum(const int32_t *seg, int top, in
 
 // ---------------------------------------------------------------- InitHisto
 
+// Builds every vertex's histogram from its neighbours' current values and
+// pushes {v : cnt(v) < core(v)} to frontier buffer `buf`.  At the start
+// (rebuild false) a vertex's value is its degree, or its given bound; in a
+// rebuild round (Jacobi round after SumHisto, in place of UpdateHisto) the
+// values are the current estimates, below the degrees.
 template <typename Off>
 __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long long *lds_scan_l,
-                           unsigned long long *lds64) {
+                           unsigned long long *lds64, int buf, bool rebuild) {
     GridState *gs = &a.st->g;
     const int lane = lane_id();
     // Block-uniform tiles of kBlock vertices (a wave takes 64 of them), so the
@@ -147,11 +164,11 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
          tile += (long long)gridDim.x * kBlock) {
         long long v = tile + threadIdx.x;
         bool valid = v < a.n;
-        // c: v's starting value, its number of buckets; d: its neighbours
-        // (equal unless the run starts from given bounds)
+        // c: v's value, its number of buckets; d: its neighbours (equal at a
+        // cold start)
         int c = valid ? a.core[v] : 0;
         long long e0 = valid ? (long long)a.off[v] : 0;
-        int d = valid && a.warm ? (int)((long long)a.off[v + 1] - e0) : c;
+        int d = valid && (a.warm || rebuild) ? (int)((long long)a.off[v + 1] - e0) : c;
         bool push = false;
         if (valid && d > 0 && d <= kSmall) {
             // one lane owns v's segment: plain read-modify-write, no atomics
@@ -198,14 +215,14 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
         __syncthreads();
         if (push) {
             unsigned long long i = (old & kSlotMask) + pre;
-            a.F[0][i] = (int)v;
-            a.FE[0][i] = (long long)(old >> kSlotBits) + epre;
-            a.FR[0][i] = e0;
+            a.F[buf][i] = (int)v;
+            a.FE[buf][i] = (long long)(old >> kSlotBits) + epre;
+            a.FR[buf][i] = e0;
         }
         bool hv = valid && d > kLdsCap;
         long long t = wave_append(hv, &gs->ctr[HS_TAIL].v);
         if (hv) {
-            a.HS[t] = (int)v;
+            a.HS[t % a.n] = (int)v;  // a ring: the counter runs on over rounds
             long long np = ((long long)d + kInitCh - 1) / kInitCh;
             unsigned long long b = atomicAdd(&gs->ctr[H_TAIL].v, (unsigned long long)np);
             for (long long j = 0; j < np; ++j) a.H[(b + j) % a.hcap] = (v << 32) | j;
@@ -239,7 +256,7 @@ __device__ void init_heavy(const HcArgs<Off> &a, unsigned long long h0, unsigned
 }
 
 template <typename Off>
-__device__ void init_heavy_check(const HcArgs<Off> &a, unsigned long long s0, unsigned long long s1) {
+__device__ void init_heavy_check(const HcArgs<Off> &a, unsigned long long s0, unsigned long long s1, int buf) {
     GridState *gs = &a.st->g;
     const long long nw = (long long)gridDim.x * kWavesPerBlock;
     for (long long base = (long long)s0 + wave_id_global() * kWave; base < (long long)s1;
@@ -255,7 +272,7 @@ __device__ void init_heavy_check(const HcArgs<Off> &a, unsigned long long s0, un
             d = (int)((long long)a.off[v + 1] - rs);  // the row, for the round's edge space
             push = a.histo[rs + c - 1] < c;
         }
-        wave_push_packed(push, v, rs, d, &gs->ctr[FET].v, 0, a.F[0], a.FE[0], a.FR[0]);
+        wave_push_packed(push, v, rs, d, &gs->ctr[FET].v, 0, a.F[buf], a.FE[buf], a.FR[buf]);
     }
 }
 
@@ -473,15 +490,24 @@ void hc_persistent(HcArgs<Off> a) {
     }
     if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
     if (timer) clk.lap(&st->phase[0].v);
-    init_histo<Off>(a, U.hist[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64);
-    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
-    const unsigned long long h_end = snap[H_TAIL], hs_end = snap[HS_TAIL];
-    init_heavy<Off>(a, 0, h_end, 0);
-    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
-    init_heavy<Off>(a, 0, h_end, 1);
-    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
-    init_heavy_check<Off>(a, 0, hs_end);
-    if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
+    // InitHisto, and in rebuild rounds the same pass over current values:
+    // rows up to kLdsCap in this pass, longer ones in pieces after it
+    // (cleared, then counted), then their frontier test.  Heavy-row lists are
+    // rings indexed by running counters, so every pass starts where the
+    // previous one ended.
+    auto build_histograms = [&](int buf, bool rebuild) -> bool {
+        const unsigned long long h0 = snap[H_TAIL], hs0 = snap[HS_TAIL];
+        init_histo<Off>(a, U.hist[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64, buf, rebuild);
+        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return false;
+        const unsigned long long h1 = snap[H_TAIL], hs1 = snap[HS_TAIL];
+        init_heavy<Off>(a, h0, h1, 0);
+        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return false;
+        init_heavy<Off>(a, h0, h1, 1);
+        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return false;
+        init_heavy_check<Off>(a, hs0, hs1, buf);
+        return grid_sync<kSnap>(gs, nb, a.limit, snap, bar);
+    };
+    if (!build_histograms(0, false)) return;
     if (timer) clk.lap(&st->phase[1].v);
 
     // Round r's frontier: entries [0, nf) of buffer r & 1, edge space [0, e1).
@@ -492,7 +518,7 @@ void hc_persistent(HcArgs<Off> a) {
     long long nf = (long long)(snap[FET] & kSlotMask);
     unsigned long long e1 = snap[FET] >> kSlotBits;
     const long long first = nf;
-    long long rounds = 0, ftotal = 0;
+    long long rounds = 0, ftotal = 0, nrebuild = 0;
     long long nmove_flushed = 0;          // this thread's moves already in moves_sched
     unsigned long long moves_seen = 0;    // block 0: moves_sched at the last record
     for (int r = 0; nf > 0; ++r) {
@@ -511,25 +537,43 @@ void hc_persistent(HcArgs<Off> a) {
         if (timer) clk.lap(&st->phase[3].v);
         const unsigned long long t_sum = timer ? wall_clock64() : 0ull;
         const unsigned long long fnext = snap[FET] & kSlotMask;  // 0: cleared this round
-        nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? (long long)e1 : 0;
-        edge_balanced(a.F[cur], a.FE[cur], a.FR[cur], a.P0, a.P1, 0, nf, 0ll, (long long)e1,
-                      a.cols, a.ndeg, eb,
-                      [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR],
-                          EbLds &L, const int (&du)[kEbR]) {
-                          int cvr[kEbR], ovr[kEbR];
+        // A round whose frontier rows cover a large share of the adjacency
+        // rebuilds every histogram from the current values instead (one
+        // InitHisto pass: a gather per entry and LDS counting, against two
+        // memory-side atomics per moved entry).  It leaves the histograms
+        // UpdateHisto would (bucket b < core[u] counts neighbours valued b,
+        // bucket core[u] those valued >= core[u]) and the same next frontier:
+        // every vertex has cnt >= core when UpdateHisto starts and cnt only
+        // falls during it, so the vertices it would push are exactly those
+        // with cnt < core after it.
+        const bool rebuild = (unsigned long long)e_round * 1000ull >= (unsigned long long)a.rebuild_permille *
+                                                                           (unsigned long long)a.m;
+        if (rebuild) {
+            nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? a.m : 0;
+            if (!build_histograms(nxt, true)) return;
+            ++nrebuild;
+            if (timer) clk.lap(&st->phase[5].v);
+        } else {
+            nedge += (blockIdx.x == 0 && threadIdx.x == 0) ? (long long)e1 : 0;
+            edge_balanced(a.F[cur], a.FE[cur], a.FR[cur], a.P0, a.P1, 0, nf, 0ll, (long long)e1,
+                          a.cols, a.ndeg, eb,
+                          [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&own)[kEbR],
+                              EbLds &L, const int (&du)[kEbR]) {
+                              int cvr[kEbR], ovr[kEbR];
 #pragma unroll
-                          for (int q = 0; q < kEbR; ++q) {
-                              cvr[q] = L.p0[own[q]];
-                              ovr[q] = L.p1[own[q]];
-                          }
-                          hc_relax<Off>(act, u, cvr, ovr, du, a, nxt, fnext, nmove);
-                      });
-        if (a.sched) {  // this round's moves, for the schedule record
-            flush_count(nmove - nmove_flushed, &st->moves_sched.v);
-            nmove_flushed = nmove;
+                              for (int q = 0; q < kEbR; ++q) {
+                                  cvr[q] = L.p0[own[q]];
+                                  ovr[q] = L.p1[own[q]];
+                              }
+                              hc_relax<Off>(act, u, cvr, ovr, du, a, nxt, fnext, nmove);
+                          });
+            if (a.sched) {  // this round's moves, for the schedule record
+                flush_count(nmove - nmove_flushed, &st->moves_sched.v);
+                nmove_flushed = nmove;
+            }
+            if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
+            if (timer) clk.lap(&st->phase[4].v);
         }
-        if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return;
-        if (timer) clk.lap(&st->phase[4].v);
         if (timer && a.sched && r < a.sched_cap) {
             pico_step *sp = a.sched + r;
             sp->key = r + 1;
@@ -541,7 +585,7 @@ void hc_persistent(HcArgs<Off> a) {
             sp->rounds = 1;
             sp->ns = (long long)((double)(wall_clock64() - t_round) * a.ns_per_tick);
             sp->scan_ns = (long long)((double)(t_sum - t_round) * a.ns_per_tick);
-            sp->reserved = 0;
+            sp->kind = rebuild ? 1 : 0;
         }
         nf = (long long)((snap[FET] & kSlotMask) - fnext);
         e1 = snap[FET] >> kSlotBits;
@@ -553,6 +597,7 @@ void hc_persistent(HcArgs<Off> a) {
         st->rounds.v = (unsigned long long)rounds;
         st->first_frontier.v = (unsigned long long)first;
         st->frontier_total.v = (unsigned long long)ftotal;
+        st->rebuilds.v = (unsigned long long)nrebuild;
     }
 }
 
@@ -783,8 +828,10 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
         return PICO_ENOMEM;
     }
     a.limit = wall_ticks(20.0);
+    a.m = m;
     a.warm = warm;
     a.warm_add = warm_add;
+    a.rebuild_permille = tune_int("PICO_HC_REBUILD_PERMILLE", kRebuildPermille);
     a.sched = sched;
     a.sched_cap = sched ? sched_cap : 0;
     a.ns_per_tick = 1e9 / (double)wall_ticks(1.0);
@@ -812,7 +859,7 @@ int run_histocore(const Off *off, const int32_t *cols, int64_t n, int64_t m, int
     if (stats) {
         stats->iterations = (int64_t)h->rounds.v;
         stats->sub_rounds = (int64_t)h->rounds.v;
-        stats->scans = 0;
+        stats->scans = (int64_t)h->rebuilds.v;
         stats->frontier_total = (int64_t)h->frontier_total.v;
         stats->k_max = 0;
         stats->edges_scanned = (int64_t)h->g.ctr[N_EDGES].v;
@@ -866,8 +913,10 @@ int run_index2core(const Off *off, const int32_t *cols, int64_t n, int64_t m, in
     h.H = nullptr;
     h.st = cv.take<HcState>(1);
     h.limit = wall_ticks(20.0);
+    h.m = m;
     h.warm = nullptr;
     h.warm_add = 0;
+    h.rebuild_permille = 0;
     h.sched = nullptr;
     h.sched_cap = 0;
     h.ns_per_tick = 0.0;

@@ -538,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
             sp->rounds = rounds - rounds_before;
             sp->ns = (long long)((double)(wall_clock64() - t_level) * a.ns_per_tick);
             sp->scan_ns = (long long)((double)(t_scan - t_level) * a.ns_per_tick);
-            sp->reserved = 0;
+            sp->kind = 0;
         }
         q_end = q1;
         e_end = e1;

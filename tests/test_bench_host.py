@@ -55,6 +55,19 @@ def test_peelone_byte_model():
     assert bench.algorithmic_bytes("peelone", {"atomics": a}, n, m, w) == n * (2 * w + 20) + 8 * m + 8 * a
 
 
+def test_histocore_byte_model_with_rebuild_rounds():
+    # a rebuild round replaces UpdateHisto's 8 per scanned entry and 16 per
+    # move by InitHisto's n(2W + 4) + 12m over the current values
+    n, m, w = 100, 600, 8
+    base = {"frontier_total": 70, "pushes_dynamic": 20, "buckets_scanned": 300, "edges_scanned": 900,
+            "atomics": 150, "scans": 0}
+    b0 = bench.algorithmic_bytes("histocore", base, n, m, w)
+    want0 = (n * (2 * w + 8) + 12 * m + 4 * 50) + (70 * (28 + 2 * w) + 4 * 300 + 8 * 900 + 16 * 150 + 4 * 20) + 4 * n
+    assert b0 == want0
+    reb = dict(base, scans=2, edges_scanned=900 + 2 * m)
+    assert bench.algorithmic_bytes("histocore", reb, n, m, w) == want0 + 2 * (n * (2 * w + 4) + 12 * m)
+
+
 def test_autotune_key_names_kernel_revision(monkeypatch):
     """The batched autotuner's cache key carries the kernel's source hash, so
     a choice timed on another revision of the kernel is not reused."""

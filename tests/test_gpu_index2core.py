@@ -39,10 +39,13 @@ def test_counts_match_oracle(gi, variant):
     assert st["atomics"] >= c["edges_hindex"]
 
 
-def test_histocore_reads_fewer_edges():
+def test_histocore_reads_fewer_edges(monkeypatch):
     """The point of Table VI: with the same rounds, HistoCore reads each
     frontier vertex's row once per round where CntCore reads it three times
-    (cnt, histogram, marking) and NbrCore recomputes whole neighbourhoods."""
+    (cnt, histogram, marking) and NbrCore recomputes whole neighbourhoods.
+    HistoCore as the paper runs it: UpdateHisto in every round, no histogram
+    rebuild rounds."""
+    monkeypatch.setenv("PICO_HC_REBUILD_PERMILLE", "2000")
     g = gg.rmat(15, 16, 106).to("cuda")
     st = {}
     for v in ("histocore", "cntcore", "nbrcore"):

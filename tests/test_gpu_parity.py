@@ -84,13 +84,17 @@ def test_large_clique_one_workgroup(algo):
 
 
 @pytest.mark.parametrize("offsets_dtype", [torch.int32, torch.int64])
-def test_paths_agree_on_schedule(offsets_dtype):
+def test_paths_agree_on_schedule(offsets_dtype, monkeypatch):
     """The one-workgroup and grid paths report the same schedule where it is
     fixed by the graph: PeelOne's levels, peeled and asserted vertices and
     k_max; HistoCore's rounds, frontier sizes, edges scanned and histogram
     moves (Theorem 2 fixes the synchronous rounds).  Scan counts may differ
     by one: the grid path ends with a scan that finds no survivor when the
-    last level's survivors were all asserted during its drain."""
+    last level's survivors were all asserted during its drain.  The grid
+    path's histogram rebuild rounds are switched off here (they read every
+    entry and move nothing); test_rebuild_rounds_keep_the_schedule covers
+    them."""
+    monkeypatch.setenv("PICO_HC_REBUILD_PERMILLE", "2000")
     g = gg.rmat(13, 16, 21).with_offsets(offsets_dtype)
     print(f"case {g.name} n={g.n} m={g.m} {offsets_dtype}", flush=True)
     for algo, keys in (("peelone", ("iterations", "frontier_total", "k_max", "pushes_dynamic",
@@ -166,15 +170,19 @@ def _check_peelone_levels(want, st, steps):
     assert (steps[:, 2] > 0).all() and (steps[:, 4] >= 0).all() and (steps[:, 7] == 0).all()
 
 
-def _check_histocore_rounds(st, steps, per_round):
+def _check_histocore_rounds(st, steps, per_round, m):
     """HistoCore's round-t frontier is the synchronous iteration's round-t
-    changed set (Theorem 2): sizes compared round by round."""
+    changed set (Theorem 2): sizes compared round by round.  Rounds that
+    rebuilt the histograms (kind 1) read all m entries and move nothing."""
     assert steps.shape[0] == st["iterations"] == len(per_round)
     assert np.array_equal(steps[:, 0], np.arange(1, len(per_round) + 1))
     assert np.array_equal(steps[:, 1], np.asarray(per_round, dtype=np.int64)), \
         f"frontier sizes {steps[:, 1].tolist()} vs synchronous rounds {list(per_round)}"
-    assert int(steps[:, 3].sum()) == st["edges_scanned"]
+    kind = steps[:, 7]
+    assert set(kind.tolist()) <= {0, 1} and int((kind == 1).sum()) == st["scans"]
+    assert int(steps[kind == 0, 3].sum()) + m * int((kind == 1).sum()) == st["edges_scanned"]
     assert int(steps[:, 2].sum()) == st["atomics"]  # histogram moves, round by round
+    assert (steps[kind == 1, 2] == 0).all()
     assert (steps[:, 4] == 1).all()
 
 
@@ -194,7 +202,7 @@ def test_schedule_matches_oracle_per_step(make):
     core, st, steps = _schedule(g, "histocore")
     assert np.array_equal(core, want)
     _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
-    _check_histocore_rounds(st, steps, per_round)
+    _check_histocore_rounds(st, steps, per_round, g.m)
 
 
 @pytest.mark.parametrize("make", [lambda: gg.er_gnp(1500, 6.0, 4), lambda: gg.rmat(10, 8, 2), lambda: gg.g1()])
@@ -231,7 +239,45 @@ def test_schedule_rmat22_full_size(golden_rmat22_jacobi):
     _check_peelone_levels(want, st, steps.numpy())
     core, st, steps = pico.coreness_schedule(g.offsets, g.cols, "histocore")
     assert np.array_equal(core.cpu().numpy(), want)
-    _check_histocore_rounds(st, steps.numpy(), [int(x) for x in gold["changed_per_round"]])
+    _check_histocore_rounds(st, steps.numpy(), [int(x) for x in gold["changed_per_round"]], g.m)
+
+
+_REBUILD_CASE = []
+
+
+def _rebuild_case():
+    """An R-MAT graph beside a star of 5,000 leaves (a row above the LDS
+    histogram size whose value falls to 1) and K_2100 (rows above it whose
+    value stays 2,099), int64 offsets; with the oracle's coreness and
+    synchronous rounds, computed once."""
+    if not _REBUILD_CASE:
+        g = gg.disjoint_union(gg.rmat(13, 16, 41), gg.star(5000), gg.complete(2100)).with_offsets(torch.int64)
+        want = oracle.bz_coreness(g.offsets, g.cols)
+        _, per_round, _ = oracle.hindex_jacobi(g.offsets, g.cols)
+        _REBUILD_CASE.append((g, want, per_round))
+    return _REBUILD_CASE[0]
+
+
+@pytest.mark.parametrize("permille", ["1", "300", "700", "2000"])
+def test_rebuild_rounds_keep_the_schedule(permille, monkeypatch):
+    """Histogram rebuild rounds in place of UpdateHisto, from every round
+    (share 1/1000) to none (2000): the same coreness, rounds and per-round
+    frontiers (the synchronous iteration's, Theorem 2); only the work counts
+    change.  Includes heavy rows (the planted block's vertices have more than
+    2,048 neighbours) and int64 offsets."""
+    monkeypatch.setenv("PICO_HC_REBUILD_PERMILLE", permille)
+    g, want, per_round = _rebuild_case()
+    print(f"case {g.name} n={g.n} m={g.m} permille={permille}", flush=True)
+    core, st, steps = _schedule(g, "histocore")
+    assert np.array_equal(core, want)
+    _check_histocore_rounds(st, steps, per_round, g.m)
+    # the rule: a round rebuilds iff its frontier rows hold >= permille / 1000 of m
+    want_kind = (steps[:, 3] * 1000 >= int(permille) * g.m).astype(np.int64)
+    assert np.array_equal(steps[:, 7], want_kind)
+    if permille == "1":
+        assert st["scans"] >= 1
+    if permille == "2000":
+        assert st["scans"] == 0
 
 
 def test_schedule_cap_and_errors():
@@ -337,15 +383,15 @@ def test_rmat22_full_size(algo):
 
 
 def test_rmat26_block_full_size():
-    """The RMAT-26 + planted-block workload at full size (int64 offsets, m >
-    2^31), in the launch configuration bench.py times: both algorithms
+    """The RMAT-26 + planted-block workload at full size (int64 offsets, m of
+    2.1 billion), in the launch configuration bench.py times: both algorithms
     against the oracle (BZ on the host over the whole graph) on every vertex;
     PeelOne's level count and k_max against the oracle's coreness; the
     properties that hold at any size as an extra."""
     import bench
     g = gg.rmat26_block(device="cuda")
     print(f"case {g.name} n={g.n} m={g.m}", flush=True)
-    assert g.offsets.dtype == torch.int64 and g.m >= 2 ** 31
+    assert g.offsets.dtype == torch.int64 and g.m > 2 ** 30
     po, st_po = pico.coreness(g.offsets, g.cols, "peelone", with_stats=True)
     hc, st_hc = pico.coreness(g.offsets, g.cols, "histocore", with_stats=True)
     props = bench.coreness_properties(g.offsets, g.cols, po)
