@@ -200,6 +200,26 @@ PICO_API int pico_coreness(const void *csr_offsets, const int32_t *csr_cols, int
                   int algo, int32_t *out_core, void *stream);
 
 /*
+ * pico_coreness_noalloc -- as pico_coreness (same arguments, same result),
+ * for callers that cannot allocate device or host memory during the call:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The workspace is a static device array of
+ * PICO_NOALLOC_SCRATCH_BYTES held by the library on every GPU it runs on
+ * until the process ends; the call allocates nothing (no hipMalloc, pinned
+ * host memory or profiling events; pico_profile_enable does not apply).
+ * Graphs whose workspace (pico_workspace_bytes for the same algo) exceeds
+ * PICO_NOALLOC_SCRATCH_BYTES get PICO_ENOMEM before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on the
+ * same GPU (several host threads, or streams not ordered with each other)
+ * race and must be serialised by the caller.  The array keeps the previous
+ * call's contents; the kernels initialise what they read.  Waits for the
+ * result before returning.
+ */
+#define PICO_NOALLOC_SCRATCH_BYTES (64ull << 20)
+PICO_API int pico_coreness_noalloc(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,
+                                   int algo, int32_t *out_core, void *stream);
+
+/*
  * pico_workspace_bytes -- bytes of device scratch that pico_coreness_ws needs
  * for a graph of n vertices and m directed entries.  Writes *bytes; returns
  * PICO_EINVAL on bad sizes or algo.

@@ -32,13 +32,15 @@ __all__ = [
     "ServerStatus", "pico_task_scratch_bytes", "pico_tasks_workspace_bytes", "pico_coreness_tasks",
     "Server", "pico_server_create", "pico_server_submit", "pico_server_progress",
     "pico_server_query", "pico_server_destroy", "pico_probe_random_access", "probe_random_access",
-    "PicoStep", "pico_coreness_schedule", "coreness_schedule",
+    "PicoStep", "pico_coreness_schedule", "coreness_schedule", "pico_coreness_noalloc",
+    "PICO_NOALLOC_SCRATCH_BYTES",
 ]
 
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
 PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE, PICO_ALGO_AUTO, PICO_OFFSETS_I64 = 0, 1, 2, 0x100
 PICO_PATH_GRID, PICO_PATH_WG = 0x200, 0x400
 PICO_PO_STATIC, PICO_PO_ROLLBACK, PICO_PO_GPP = 0x800, 0x1000, 0x2000
+PICO_NOALLOC_SCRATCH_BYTES = 64 << 20  # static workspace of pico_coreness_noalloc
 PATHS = {None: 0, "auto": 0, "grid": PICO_PATH_GRID, "wg": PICO_PATH_WG}
 ALGOS = {"peelone": PICO_ALGO_PEELONE, "histocore": PICO_ALGO_HISTOCORE}
 # single-graph calls may also ask for the per-graph choice between the two
@@ -59,7 +61,8 @@ EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update",
                     "pico_coreness_batched", "pico_task_scratch_bytes",
                     "pico_tasks_workspace_bytes", "pico_coreness_tasks", "pico_server_create",
                     "pico_server_submit", "pico_server_progress", "pico_server_query",
-                    "pico_server_destroy", "pico_probe_random_access", "pico_coreness_schedule")
+                    "pico_server_destroy", "pico_probe_random_access", "pico_coreness_schedule",
+                    "pico_coreness_noalloc")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpico.so")
@@ -180,6 +183,8 @@ def load_library():
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.pico_coreness.argtypes = [vp, vp, i64, i64, i32, vp, vp]
     lib.pico_coreness.restype = i32
+    lib.pico_coreness_noalloc.argtypes = [vp, vp, i64, i64, i32, vp, vp]
+    lib.pico_coreness_noalloc.restype = i32
     lib.pico_coreness_ws.argtypes = [vp, vp, i64, i64, i32, vp, vp, ctypes.c_size_t,
                                      ctypes.POINTER(PicoStats), vp]
     lib.pico_coreness_ws.restype = i32
@@ -276,6 +281,12 @@ def pico_coreness(csr_offsets, csr_cols, n: int, m: int, algo: int, out_core, st
     lib = load_library()
     return lib.pico_coreness(_ptr(csr_offsets), _ptr(csr_cols), n, m, algo, _ptr(out_core),
                              _stream(stream))
+
+
+def pico_coreness_noalloc(csr_offsets, csr_cols, n: int, m: int, algo: int, out_core, stream=None) -> int:
+    """C ``pico_coreness_noalloc``; returns the status code (does not raise)."""
+    return load_library().pico_coreness_noalloc(_ptr(csr_offsets), _ptr(csr_cols), n, m, algo,
+                                                _ptr(out_core), _stream(stream))
 
 
 def pico_workspace_bytes(n: int, m: int, algo: int) -> int:

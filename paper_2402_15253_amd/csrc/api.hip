@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -25,7 +26,20 @@ void set_error(const char *fmt, ...) {
 
 void clear_error() { g_err[0] = 0; }
 
+// Set while pico_coreness_noalloc runs on this host thread: read-backs go to
+// a fixed thread-local buffer instead of pinned memory, and no profiling
+// events are created.
+static thread_local bool g_no_alloc = false;
+
 void *host_scratch(size_t bytes) {
+    if (g_no_alloc) {
+        alignas(256) static thread_local unsigned char fixed[1 << 14];
+        if (bytes > sizeof(fixed)) {
+            set_error("read-back of %zu bytes exceeds the fixed host buffer (%zu)", bytes, sizeof(fixed));
+            return nullptr;
+        }
+        return fixed;
+    }
     static thread_local void *buf = nullptr;
     static thread_local size_t cap = 0;
     if (bytes > cap) {
@@ -308,7 +322,7 @@ int check_device() {
 }
 
 int prof_begin(const char *name, hipStream_t s) {
-    if (!g_prof.on) return -1;
+    if (!g_prof.on || g_no_alloc) return -1;
     ProfRec r{name, prof_event(), prof_event()};
     if (!r.start || !r.stop) return -1;
     if (hipEventRecord(r.start, s) != hipSuccess) return -1;
@@ -323,6 +337,47 @@ void prof_end(int rec, hipStream_t s) {
 }  // namespace pico
 
 using namespace pico;
+
+// Workspace of pico_coreness_noalloc: one array per GPU, held until the
+// process ends.  Host code never passes its name to a kernel (on the host it
+// is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[PICO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The calling thread's current device's copy of `scratch`.
+int scratch_for_current_device(void **out) {
+    int dev = -1;
+    PICO_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device ordinal %d out of range for the static scratch table", dev);
+        return PICO_ENOTSUP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+            return PICO_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PICO_OK;
+}
+
+struct NoAllocScope {
+    NoAllocScope() { g_no_alloc = true; }
+    ~NoAllocScope() { g_no_alloc = false; }
+};
+
+}  // namespace
 
 static bool tune_ok(const pico_batch_tune *tune) {
     if (tune && tune->help_min_vertices < -1) {
@@ -539,6 +594,31 @@ int pico_coreness(const void *csr_offsets, const int32_t *csr_cols, int64_t n, i
     }
     PICO_HIP_TRY(hipStreamSynchronize(s));
     return prof_resolve();
+}
+
+int pico_coreness_noalloc(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m, int algo,
+                          int32_t *out_core, void *stream) {
+    clear_error();
+    int rc = check_args(csr_offsets, csr_cols, n, m, algo, out_core);
+    if (rc) return rc;
+    if (n == 0) return PICO_OK;
+    const size_t need = ws_bytes_for(n, m, algo);
+    if (need > (size_t)PICO_NOALLOC_SCRATCH_BYTES) {
+        set_error("graph needs %zu bytes of scratch; the static scratch holds %zu (n=%lld, m=%lld)", need,
+                  (size_t)PICO_NOALLOC_SCRATCH_BYTES, (long long)n, (long long)m);
+        return PICO_ENOMEM;
+    }
+    rc = check_device();
+    if (rc) return rc;
+    void *ws = nullptr;
+    rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+    NoAllocScope scope;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = dispatch(csr_offsets, csr_cols, n, m, algo, out_core, ws, need, nullptr, s);
+    if (rc) return rc;
+    PICO_HIP_TRY(hipStreamSynchronize(s));
+    return PICO_OK;
 }
 
 int pico_batched_workspace_bytes(int64_t num_graphs, int64_t total_n, int64_t total_m, int algo,
