@@ -267,13 +267,13 @@ def bench_batched(args, pico, torch, np):
     order = pico.largest_first(b.vptr)
     algos = args.algos.split(",")
     views = graph_views(b, torch)
-    ws_plain_bytes = max(pico.pico_workspace_bytes(v[2], v[3], pico.ALGOS[a] | pico.PICO_OFFSETS_I64)
+    ws_plain_bytes = max(pico.pico_workspace_bytes(v[2], v[3], pico.SINGLE_ALGOS[a] | pico.PICO_OFFSETS_I64)
                          for v in views for a in algos)
     ws_plain = torch.empty(ws_plain_bytes, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     per, outs, kern = {}, {}, {}
     for a in algos:
-        code = pico.ALGOS[a]
+        code = pico.BATCH_ALGOS[a]
         tune = None
         if not args.no_tune:
             from paper_2402_15253_amd import autotune
@@ -306,7 +306,7 @@ def bench_batched(args, pico, torch, np):
         pico.pico_profile_enable(False)
         # the plain method: one call per graph, back to back on the same stream
         out_p = torch.empty(total_n, dtype=torch.int32, device=dev)
-        pcode = code | pico.PICO_OFFSETS_I64
+        pcode = pico.SINGLE_ALGOS[a] | pico.PICO_OFFSETS_I64
 
         def plain_pass():
             for off, cols, n, m, x0 in views:
@@ -334,7 +334,9 @@ def bench_batched(args, pico, torch, np):
                   "speedup_vs_plain": round(t_plain / t_batched, 2), "identical_to_plain": same,
                   "batched_gteps": round(total_m / t_batched / 1e9, 3),
                   "tune": tune.as_dict() if tune else None, "stats": sd}
-        if "batched_kernel" in prof:
+        # (an AUTO call mixes the two algorithms' counters over two launches:
+        # no single byte model, so no roofline for it)
+        if "batched_kernel" in prof and a != "auto":
             launches, t_ms = prof["batched_kernel"]
             avg = t_ms / max(launches, 1)
             kern[a] = _roofline("batched_kernel", algorithmic_bytes(a, _batch_stats_as_plain(sd),

@@ -353,6 +353,8 @@ typedef struct pico_batch_stats {
     int32_t blocks_per_cu;   /* resident workgroups per compute unit used */
     int64_t helped_graphs;   /* graphs decomposed with their phases open to helpers */
     int64_t help_chunks;     /* phase chunks run by helping workgroups */
+    int64_t histocore_graphs;/* graphs decomposed by HistoCore (under PICO_ALGO_AUTO:
+                                the ones the per-graph choice gave it) */
 } pico_batch_stats;
 
 /*
@@ -376,13 +378,22 @@ PICO_API int pico_batched_workspace_bytes(int64_t num_graphs, int64_t total_n, i
  *   order        int32[num_graphs] processing order (e.g. largest graph first),
  *                or NULL for 0..num_graphs-1
  *   out_core     int32[total_n], caller-owned
- * `algo` is PICO_ALGO_PEELONE or PICO_ALGO_HISTOCORE (offsets are always
- * int64 here; PICO_OFFSETS_I64 is accepted and ignored).  Each graph must be
- * a simple undirected graph with fewer than 2^31 vertices and edges.  The
- * workspace (>= pico_batched_workspace_bytes, 256-byte aligned) is
- * caller-owned.  The call only enqueues work on `stream` unless `stats` is
- * non-NULL, in which case it waits and fills it; out_core is valid once the
- * stream has completed.
+ * `algo` is PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE or PICO_ALGO_AUTO (offsets
+ * are always int64 here; PICO_OFFSETS_I64 is accepted and ignored).
+ * PICO_ALGO_AUTO chooses per graph on the device (the hybrid the paper leaves
+ * to future work, Section VII): HistoCore for a graph in which fewer than
+ * 1/64 of up to 64 evenly spaced sampled vertices are in HistoCore's first
+ * frontier (cnt(v) < deg(v), Theorem 2: the degrees are then nearly the
+ * coreness), PeelOne otherwise -- with one workgroup per graph PeelOne's
+ * levels are cheap and it is the faster algorithm elsewhere; the two groups
+ * run as two launches on `stream`.  Each graph must be a simple undirected
+ * graph with fewer than 2^31 vertices and edges.  The workspace (>=
+ * pico_batched_workspace_bytes for the same algo, 256-byte aligned) is
+ * caller-owned; it begins with one int32 status word per graph (see
+ * pico_batch_status).  The call only enqueues work on `stream` unless `stats`
+ * is non-NULL, in which case it waits, fills it, and returns PICO_EHIP if a
+ * graph was left unfinished (a wait bound expired) or PICO_EINVAL if a graph's
+ * vertex range was invalid; out_core is valid once the stream has completed.
  */
 PICO_API int pico_coreness_batched(const int64_t *graph_vptr, const int64_t *csr_offsets,
                                    const int32_t *csr_cols, int64_t num_graphs, int64_t total_n,
@@ -414,12 +425,13 @@ typedef struct pico_task {
 } pico_task;
 
 /* pico_task_scratch_bytes -- per-task scratch for a graph of n vertices and m
-   directed entries: 16 n bytes for PeelOne, 20 n + 4 m for HistoCore (each
-   array rounded up to 256 bytes). */
+   directed entries: 16 n bytes for PeelOne, 20 n + 4 m for HistoCore and for
+   PICO_ALGO_AUTO (each array rounded up to 256 bytes). */
 PICO_API int pico_task_scratch_bytes(int64_t n, int64_t m, int algo, size_t *bytes);
 
 /* pico_tasks_workspace_bytes -- device workspace of pico_coreness_tasks for a
-   list of num_tasks descriptors (task tables and counters). */
+   list of num_tasks descriptors (status words first, then task tables and
+   counters), for any algo. */
 PICO_API int pico_tasks_workspace_bytes(int64_t num_tasks, size_t *bytes);
 
 /*
@@ -429,16 +441,37 @@ PICO_API int pico_tasks_workspace_bytes(int64_t num_tasks, size_t *bytes);
  * HOST array, copied to the workspace on `stream` during the call and free to
  * reuse on return.  Arguments are checked on the host: n in [0, 2^31), m >= 0,
  * pointers present, scratch large enough and aligned (PICO_EINVAL /
- * PICO_ENOMEM).  Enqueues only, unless `stats` is non-NULL (then waits).
+ * PICO_ENOMEM).  `algo` as for pico_coreness_batched (PICO_ALGO_AUTO chooses
+ * per task; its tasks need HistoCore-sized scratch).  Enqueues only, unless
+ * `stats` is non-NULL (then waits, and reports unfinished tasks as
+ * pico_coreness_batched does); per-task outcomes: pico_batch_status.
  */
 PICO_API int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int algo,
                                  const pico_batch_tune *tune, void *workspace, size_t ws_bytes,
                                  pico_batch_stats *stats, void *stream);
 
 /*
+ * pico_batch_status -- outcome of every graph of the last pico_coreness_batched
+ * or pico_coreness_tasks call on `workspace`: waits for `stream` (the stream
+ * of that call), then copies `count` int32 status words into `status` (host
+ * array; NULL to get only the summary), one per graph in the caller's
+ * numbering (graph index of the packed batch, position in the task list):
+ *   PICO_OK      decomposed; its out_core is the coreness
+ *   PICO_EHIP    not finished: a wait inside the launch reached its bound
+ *                (a minute) and the graph was left incomplete
+ *   PICO_EINVAL  not decomposed: invalid vertex range (packed batches)
+ * Returns PICO_OK if every word is PICO_OK, else the first other status, with
+ * the counts in pico_last_error().  For callers that enqueue without stats.
+ */
+PICO_API int pico_batch_status(const void *workspace, size_t ws_bytes, int64_t count, int32_t *status,
+                               void *stream);
+
+/*
  * Request server: continuous batching of decomposition requests on one GPU.
  * Requests name a device-resident graph (int64 offsets, as in pico_task) and
- * a device output.  A request is admitted once its scratch
+ * a device output.  The server's algo may be PICO_ALGO_AUTO (a choice per
+ * request, as in pico_coreness_batched; requests then reserve HistoCore-sized
+ * scratch).  A request is admitted once its scratch
  * (pico_task_scratch_bytes) fits in the caller's HBM arena (first come,
  * first served within its size class); admitted requests are launched
  * together, largest first, as one batched-kernel call on a free launch slot
@@ -454,7 +487,8 @@ PICO_API int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int 
 typedef struct pico_server pico_server;
 
 typedef struct pico_server_config {
-    int32_t algo;                  /* PICO_ALGO_PEELONE or PICO_ALGO_HISTOCORE */
+    int32_t algo;                  /* PICO_ALGO_PEELONE, PICO_ALGO_HISTOCORE or
+                                      PICO_ALGO_AUTO */
     int32_t max_inflight;          /* launch slots (streams), 1..64 */
     int64_t max_tasks_per_launch;  /* requests per launch, >= 1 */
     void *arena;                   /* device, 256-byte aligned, caller-owned: the
@@ -477,7 +511,9 @@ typedef struct pico_request {
 
 typedef struct pico_completion {
     int64_t tag;
-    int32_t status;          /* PICO_OK */
+    int32_t status;          /* PICO_OK, or PICO_EHIP if the request's launch left
+                                it unfinished (a wait bound expired); its
+                                out_core is then not the coreness */
     int32_t reserved;
     uint64_t t_submit_ns;    /* host steady-clock times: submit, launch, and */
     uint64_t t_launch_ns;    /* when progress saw the launch complete */

@@ -33,7 +33,7 @@ __all__ = [
     "Server", "pico_server_create", "pico_server_submit", "pico_server_progress",
     "pico_server_query", "pico_server_destroy", "pico_probe_random_access", "probe_random_access",
     "PicoStep", "pico_coreness_schedule", "coreness_schedule", "pico_coreness_noalloc",
-    "PICO_NOALLOC_SCRATCH_BYTES",
+    "PICO_NOALLOC_SCRATCH_BYTES", "BATCH_ALGOS", "pico_batch_status", "batch_status",
 ]
 
 PICO_OK, PICO_EINVAL, PICO_ENOMEM, PICO_EHIP, PICO_ENOTSUP, PICO_EBADCSR = 0, -1, -2, -3, -4, -5
@@ -43,6 +43,8 @@ PICO_PO_STATIC, PICO_PO_ROLLBACK, PICO_PO_GPP = 0x800, 0x1000, 0x2000
 PICO_NOALLOC_SCRATCH_BYTES = 64 << 20  # static workspace of pico_coreness_noalloc
 PATHS = {None: 0, "auto": 0, "grid": PICO_PATH_GRID, "wg": PICO_PATH_WG}
 ALGOS = {"peelone": PICO_ALGO_PEELONE, "histocore": PICO_ALGO_HISTOCORE}
+# batched, task-list and server calls may also choose per graph
+BATCH_ALGOS = {**ALGOS, "auto": PICO_ALGO_AUTO}
 # single-graph calls may also ask for the per-graph choice between the two
 SINGLE_ALGOS = {**ALGOS, "auto": PICO_ALGO_AUTO}
 ALGO_NAMES = {PICO_ALGO_PEELONE: "peelone", PICO_ALGO_HISTOCORE: "histocore"}
@@ -62,7 +64,7 @@ EXPORTED_SYMBOLS = ("pico_coreness", "pico_coreness_ws", "pico_coreness_update",
                     "pico_tasks_workspace_bytes", "pico_coreness_tasks", "pico_server_create",
                     "pico_server_submit", "pico_server_progress", "pico_server_query",
                     "pico_server_destroy", "pico_probe_random_access", "pico_coreness_schedule",
-                    "pico_coreness_noalloc")
+                    "pico_coreness_noalloc", "pico_batch_status")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpico.so")
@@ -118,7 +120,7 @@ class BatchStats(ctypes.Structure):
                 ("pushes", ctypes.c_int64), ("lds_graphs", ctypes.c_int64),
                 ("workgroups", ctypes.c_int64), ("lds_bytes", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("helped_graphs", ctypes.c_int64),
-                ("help_chunks", ctypes.c_int64)]
+                ("help_chunks", ctypes.c_int64), ("histocore_graphs", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -221,6 +223,8 @@ def load_library():
     lib.pico_coreness_tasks.argtypes = [ctypes.POINTER(Task), i64, i32, ctypes.POINTER(BatchTune), vp,
                                         ctypes.c_size_t, ctypes.POINTER(BatchStats), vp]
     lib.pico_coreness_tasks.restype = i32
+    lib.pico_batch_status.argtypes = [vp, ctypes.c_size_t, i64, vp, vp]
+    lib.pico_batch_status.restype = i32
     lib.pico_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.pico_server_create.restype = i32
     lib.pico_server_submit.argtypes = [vp, ctypes.POINTER(Request)]
@@ -405,6 +409,22 @@ def pico_coreness_batched(graph_vptr, csr_offsets, csr_cols, num_graphs: int, to
                                      _stream(stream))
 
 
+def pico_batch_status(workspace, ws_bytes: int, count: int, status=None, stream=None) -> int:
+    """C ``pico_batch_status`` (``status``: host int32 numpy array of ``count``
+    entries, or None); returns the status code."""
+    ptr = status.ctypes.data if status is not None else None
+    return load_library().pico_batch_status(_ptr(workspace), ws_bytes, count, ptr, _stream(stream))
+
+
+def batch_status(workspace, count: int, stream=None):
+    """(summary status, int32 numpy array of per-graph status words) of the
+    last batched or task-list call on ``workspace``."""
+    import numpy as np
+    out = np.zeros(max(count, 0), dtype=np.int32)
+    rc = pico_batch_status(workspace, workspace.numel(), count, out if count else None, stream)
+    return rc, out
+
+
 def largest_first(vptr: torch.Tensor) -> torch.Tensor:
     """Processing order for a batch: graphs by decreasing vertex count."""
     sizes = vptr[1:] - vptr[:-1]
@@ -416,7 +436,7 @@ def coreness_batched(batch, algo="peelone", *, order="largest_first", tune=None,
     """Coreness of every vertex of a device-resident packed batch (object with
     vptr, offsets, cols tensors).  Raises PicoError on failure; waits for the
     result when with_stats is set, otherwise returns once enqueued."""
-    a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    a = BATCH_ALGOS[algo] if isinstance(algo, str) else int(algo)
     G = batch.vptr.numel() - 1
     total_n = batch.offsets.numel() - 1
     total_m = batch.cols.numel()
@@ -606,7 +626,7 @@ class Server:
         lib = load_library()
         self._arena = torch.empty(max(arena_bytes, 256), dtype=torch.uint8, device=device or "cuda")
         cfg = ServerConfig()
-        cfg.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        cfg.algo = BATCH_ALGOS[algo] if isinstance(algo, str) else int(algo)
         cfg.max_inflight = max_inflight
         cfg.max_tasks_per_launch = max_tasks_per_launch
         cfg.arena = self._arena.data_ptr()

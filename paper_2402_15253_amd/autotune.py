@@ -25,7 +25,7 @@ import time
 
 import torch
 
-from . import (ALGOS, BatchStats, BatchTune, PicoError, PICO_OK, pico_batched_workspace_bytes,
+from . import (BATCH_ALGOS, BatchStats, BatchTune, PicoError, PICO_OK, pico_batched_workspace_bytes,
                pico_coreness_batched, pico_last_error)
 from .profiling import source_hash
 
@@ -80,7 +80,7 @@ def tune_batched(batch, algo: str, *, order=None, reps: int = 2, use_cache: bool
         if log:
             log(f"autotune {algo}: cached {c}")
         return BatchTune(c["lds_bytes"], c["blocks_per_cu"], c["sum_wave_min"], c.get("help_min_vertices", 0))
-    code = ALGOS[algo]
+    code = BATCH_ALGOS[algo]
     G = batch.vptr.numel() - 1
     n, m = batch.offsets.numel() - 1, batch.cols.numel()
     wsb = pico_batched_workspace_bytes(G, n, m, code)
@@ -123,7 +123,7 @@ def tune_batched(batch, algo: str, *, order=None, reps: int = 2, use_cache: bool
             dt = measure(t)
             if dt < best_t:
                 best, best_t = t, dt
-    if algo == "histocore":
+    if algo in ("histocore", "auto"):
         base = best
         for sw in SUM_WAVE_CANDIDATES:
             t = BatchTune(base.lds_bytes, base.blocks_per_cu, sw)

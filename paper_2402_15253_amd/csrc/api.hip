@@ -625,7 +625,7 @@ int pico_batched_workspace_bytes(int64_t num_graphs, int64_t total_n, int64_t to
                                  size_t *bytes) {
     clear_error();
     int a = algo & PICO_ALGO_MASK;
-    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) || num_graphs < 0 || total_n < 0 ||
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) || num_graphs < 0 || total_n < 0 ||
         total_m < 0 || !bytes) {
         set_error("bad arguments to pico_batched_workspace_bytes");
         return PICO_EINVAL;
@@ -642,7 +642,7 @@ int pico_coreness_batched(const int64_t *graph_vptr, const int64_t *csr_offsets,
     clear_error();
     if (stats) memset(stats, 0, sizeof(*stats));
     int a = algo & PICO_ALGO_MASK;
-    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) ||
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) ||
         (algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64)) != 0) {
         set_error("unknown algo %d", algo);
         return PICO_EINVAL;
@@ -688,8 +688,8 @@ int pico_coreness_batched(const int64_t *graph_vptr, const int64_t *csr_offsets,
 int pico_task_scratch_bytes(int64_t n, int64_t m, int algo, size_t *bytes) {
     clear_error();
     int a = algo & PICO_ALGO_MASK;
-    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) || n < 0 || n > INT32_MAX || m < 0 ||
-        !bytes) {
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) || n < 0 || n > INT32_MAX ||
+        m < 0 || !bytes) {
         set_error("bad arguments to pico_task_scratch_bytes");
         return PICO_EINVAL;
     }
@@ -713,7 +713,7 @@ int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int algo,
     clear_error();
     if (stats) memset(stats, 0, sizeof(*stats));
     int a = algo & PICO_ALGO_MASK;
-    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) ||
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) ||
         (algo & ~(PICO_ALGO_MASK | PICO_OFFSETS_I64)) != 0) {
         set_error("unknown algo %d", algo);
         return PICO_EINVAL;
@@ -771,6 +771,39 @@ int pico_coreness_tasks(const pico_task *tasks, int64_t num_tasks, int algo,
         return prof_resolve();
     }
     return PICO_OK;
+}
+
+int pico_batch_status(const void *workspace, size_t ws_bytes, int64_t count, int32_t *status, void *stream) {
+    clear_error();
+    if (count < 0 || (count > 0 && !workspace) || ws_bytes < (size_t)count * 4) {
+        set_error("bad arguments to pico_batch_status (count %lld, %zu workspace bytes)", (long long)count,
+                  ws_bytes);
+        return PICO_EINVAL;
+    }
+    if (count == 0) return PICO_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> host;
+    int32_t *dst = status;
+    if (!dst) {
+        host.resize((size_t)count);
+        dst = host.data();
+    }
+    PICO_HIP_TRY(hipStreamSynchronize(s));
+    PICO_HIP_TRY(hipMemcpy(dst, status_words(workspace), sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost));
+    int64_t unfinished = 0, invalid = 0, other = 0;
+    int first = PICO_OK;
+    for (int64_t i = 0; i < count; ++i) {
+        const int v = dst[i];
+        if (v == PICO_OK) continue;
+        if (first == PICO_OK) first = v == PICO_EHIP || v == PICO_EINVAL ? v : PICO_EHIP;
+        if (v == PICO_EHIP) ++unfinished;
+        else if (v == PICO_EINVAL) ++invalid;
+        else ++other;
+    }
+    if (first != PICO_OK)
+        set_error("%lld graphs unfinished, %lld with an invalid vertex range, %lld with an unknown status word",
+                  (long long)unfinished, (long long)invalid, (long long)other);
+    return first;
 }
 
 int pico_validate_csr(const void *csr_offsets, const int32_t *csr_cols, int64_t n, int64_t m,

@@ -105,6 +105,7 @@ struct BatchState {
     Line helped;    // graphs decomposed with the board open to helpers
     Line helpchunks;
     Line stuck;     // phases whose helpers did not finish within the wait bound
+    Line chose_hc;  // PICO_ALGO_AUTO: graphs the choice gave to HistoCore
     unsigned long long open[kOpen];  // board: job index + 1, or 0
     Job jobs[kMaxGrid];
 };
@@ -119,7 +120,7 @@ struct TaskT {
     long long e0;
     int32_t *out, *core, *L0, *L1, *L2, *oldcore, *histo;
     int n;
-    int pad;
+    int slot;  // index of the graph's status word, or -1 (no status: a hole or a single graph)
 };
 using Task = TaskT<long long>;
 
@@ -131,6 +132,7 @@ struct BatchArgs {
     int help_min;      // graphs of at least this many vertices (global tier) take helpers; 0 = never
     unsigned long long limit;  // bound on every wait (wall-clock ticks)
     BatchState *st;
+    int32_t *status;  // per graph: PICO_EHIP until it is finished, then PICO_OK (PICO_EINVAL stays)
 };
 
 // Scratch layout of one public task: core, L0, L1, L2 (n each), then for
@@ -1008,6 +1010,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
     __shared__ LeadLds sh;
     __shared__ long long claim;
     Counts c;
+    bool stop = false;
     while (true) {
         if (threadIdx.x == 0) claim = (long long)atomicAdd(&a.st->next.v, 1ull);
         __syncthreads();
@@ -1023,9 +1026,21 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
             decompose<kAlgo>(t, a.lds_cap, a.sum_wave_min, w, X, c);
         }
         __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(&a.st->finished.v, 1ull);
+        // A leader that gave up waiting for a helper left its graph unfinished
+        // (status stays PICO_EHIP).  It takes no further graph and does not
+        // help: helpers still inside a chunk of its last phase may yet add to
+        // its job record's counters, which no later phase may then use.
+        const bool stuck = helped && sh.err;
+        if (threadIdx.x == 0) {
+            atomicAdd(&a.st->finished.v, 1ull);
+            if (!stuck && t.slot >= 0) atomicCAS(&a.status[t.slot], (int)PICO_EHIP, (int)PICO_OK);
+        }
+        if (stuck) {
+            stop = true;
+            break;
+        }
     }
-    if (a.help_min > 0) help<kAlgo>(a, sh, X, c);
+    if (a.help_min > 0 && !stop) help<kAlgo>(a, sh, X, c);
     // per-thread counts: atomics, edges, buckets, pushes; per-workgroup
     // (uniform, thread 0's): levels, frontier, lds graphs
     const long long s_atom = wave_sum64(c.atomics), s_edges = wave_sum64(c.edges);
@@ -1116,22 +1131,25 @@ struct PackedArrays {
 
 // Task j of a packed batch: graph order[j] (or j), its rows and columns in
 // place, its scratch at its global vertex / position range.
-__global__ void packed_tasks(PackedArrays p, Task *tasks, BatchState *st) {
+__global__ void packed_tasks(PackedArrays p, Task *tasks, BatchState *st, int32_t *status) {
     const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= p.G) return;
     const long long g = p.order ? (long long)p.order[j] : j;
     Task t;
     const long long x0 = p.vptr[g];
     long long n = p.vptr[g + 1] - x0;
+    int32_t s0 = PICO_EHIP;  // not finished (yet)
     if (n < 0 || n > INT_MAX) {
         atomicAdd(&st->bad.v, 1ull);
         n = 0;
+        s0 = PICO_EINVAL;
     }
+    status[g] = s0;
     t.off = p.off + x0;
     t.cols = p.cols;
     t.e0 = p.off[x0];
     t.n = (int)n;
-    t.pad = 0;
+    t.slot = (int)g;
     t.out = p.out + x0;
     t.core = p.core + x0;
     t.L0 = p.L0 + x0;
@@ -1143,9 +1161,10 @@ __global__ void packed_tasks(PackedArrays p, Task *tasks, BatchState *st) {
 }
 
 
-__global__ void public_tasks(const pico_task *pt, long long T, int histocore, Task *tasks) {
+__global__ void public_tasks(const pico_task *pt, long long T, int histocore, Task *tasks, int32_t *status) {
     const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= T) return;
+    status[j] = PICO_EHIP;  // not finished (yet)
     const pico_task p = pt[j];
     Task t;
     const long long n = p.n;
@@ -1153,7 +1172,7 @@ __global__ void public_tasks(const pico_task *pt, long long T, int histocore, Ta
     t.cols = p.cols;
     t.e0 = n > 0 ? t.off[0] : 0;
     t.n = (int)n;
-    t.pad = 0;
+    t.slot = (int)j;
     t.out = p.out_core;
     int32_t *s = static_cast<int32_t *>(p.scratch);
     const long long an = task_al(n);
@@ -1164,6 +1183,67 @@ __global__ void public_tasks(const pico_task *pt, long long T, int histocore, Ta
     t.oldcore = histocore ? s + 4 * an : nullptr;
     t.histo = histocore ? s + 5 * an : nullptr;
     tasks[j] = t;
+}
+
+// PICO_ALGO_AUTO over a task table: per graph, PeelOne or HistoCore.  With
+// one workgroup per graph PeelOne's levels cost only workgroup barriers, and
+// it was the faster algorithm on all but a few hundred-vertex graphs of the
+// 4,096-graph mixed batch (by tens of microseconds); HistoCore wins where its
+// first frontier is (nearly) empty -- the degrees are then (nearly) the
+// coreness and InitHisto all but finishes, while PeelOne still walks every
+// level (regular components, unions of cliques; Table VII's cases where l2
+// is far below l1).  One workgroup per graph samples up to kChooseSamples
+// evenly spaced vertices of degree 1..kChooseMaxDeg, a wave each, and counts
+// those with cnt(v) < deg(v) (Theorem 2 with core = deg); fewer than 1/64 in
+// the frontier gives HistoCore.
+constexpr int kChooseSamples = 64;
+constexpr int kChooseMaxDeg = 1024;
+
+__global__ __launch_bounds__(kBlock) void choose_tasks(const Task *tasks, long long T, int32_t *choice,
+                                                       BatchState *st) {
+    __shared__ unsigned cnt[2];
+    for (long long j = blockIdx.x; j < T; j += gridDim.x) {
+        const Task t = tasks[j];
+        if (threadIdx.x == 0) cnt[0] = cnt[1] = 0u;
+        __syncthreads();
+        const int S = t.n < kChooseSamples ? t.n : kChooseSamples;
+        for (int q = (int)(threadIdx.x >> 6); q < S; q += kWavesPerBlock) {
+            const long long v = (long long)q * t.n / S;
+            const long long e0 = t.off[v], d = t.off[v + 1] - e0;
+            if (d == 0 || d > kChooseMaxDeg) continue;  // uniform across the wave
+            long long ge = 0;
+            for (long long e = lane_id(); e < d; e += kWave) {
+                const int u = t.cols[e0 + e];
+                ge += (t.off[u + 1] - t.off[u]) >= d ? 1 : 0;
+            }
+            ge = wave_sum64(ge);
+            if (lane_id() == 0) {
+                atomicAdd(&cnt[0], 1u);
+                if (ge < d) atomicAdd(&cnt[1], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const bool hc = cnt[0] > 0u && cnt[1] * 64u < cnt[0];
+            choice[j] = hc ? PICO_ALGO_HISTOCORE : PICO_ALGO_PEELONE;
+            if (hc) atomicAdd(&st->chose_hc.v, 1ull);
+        }
+        __syncthreads();
+    }
+}
+
+// The two per-algorithm tables of an AUTO launch: each keeps the caller's
+// order, with the other algorithm's graphs as empty holes (no status word).
+__global__ void split_tasks(const Task *all, long long T, const int32_t *choice, Task *po, Task *hc) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= T) return;
+    const Task t = all[j];
+    Task hole = t;
+    hole.n = 0;
+    hole.slot = -1;
+    const bool h = choice[j] == PICO_ALGO_HISTOCORE;
+    po[j] = h ? hole : t;
+    hc[j] = h ? t : hole;
 }
 
 struct Launch {
@@ -1205,8 +1285,11 @@ constexpr long long kHelpersPerBig = 32;  // extra workgroups per large task in 
 
 // want: workgroups wanted (the task count, plus helpers for large tasks);
 // the grid is the smaller of that and what the device holds.
+// chose_hc (optional): with stats, receives the AUTO choice count the state
+// holds.
 int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune *tune,
-                 BatchState *st, pico_batch_stats *stats, hipStream_t stream, long long want) {
+                 BatchState *st, int32_t *status, pico_batch_stats *stats, hipStream_t stream,
+                 long long want, long long *chose_hc = nullptr) {
     Launch L;
     const int help_min = help_min_of(tune);
     const bool hc = algo == PICO_ALGO_HISTOCORE;
@@ -1221,8 +1304,12 @@ int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune
     a.lds_cap = L.lds_bytes / 4;
     a.sum_wave_min = tune && tune->sum_wave_min > 0 ? tune->sum_wave_min : kSumWaveMinDefault;
     a.help_min = help_min;
-    a.limit = wall_ticks(60.0);
+    // every wait gives up after a minute (PICO_BATCH_WAIT_US: a shorter bound,
+    // for tests of the give-up path)
+    const int wait_us = tune_int("PICO_BATCH_WAIT_US", 0);
+    a.limit = wait_us > 0 ? wall_ticks(wait_us * 1e-6) : wall_ticks(60.0);
     a.st = st;
+    a.status = status;
     int rec = prof_begin("batched_kernel", stream);
     if (hc)
         hipLaunchKernelGGL(batched_kernel<PICO_ALGO_HISTOCORE>, dim3((unsigned)L.blocks), dim3(kBlock),
@@ -1251,6 +1338,8 @@ int launch_tasks(const Task *tasks, long long T, int algo, const pico_batch_tune
         stats->blocks_per_cu = L.blocks_per_cu;
         stats->helped_graphs = (int64_t)h->helped.v;
         stats->help_chunks = (int64_t)h->helpchunks.v;
+        stats->histocore_graphs = algo == PICO_ALGO_HISTOCORE ? (int64_t)T : 0;
+        if (chose_hc) *chose_hc = (long long)h->chose_hc.v;
         if (h->stuck.v) {
             set_error("%llu helped phases did not finish within the wait bound", (unsigned long long)h->stuck.v);
             return PICO_EHIP;
@@ -1357,7 +1446,7 @@ int run_small(const Off *off, const int32_t *cols, int64_t n, int64_t m, int alg
     t.cols = cols;
     t.e0 = 0;
     t.n = (int)n;
-    t.pad = 0;
+    t.slot = -1;
     t.out = out;
     t.core = cv.take<int32_t>(n);  // values live in LDS; unused
     t.L0 = cv.take<int32_t>(n);
@@ -1403,10 +1492,15 @@ template int run_small<int32_t>(const int32_t *, const int32_t *, int64_t, int64
 template int run_small<int64_t>(const int64_t *, const int32_t *, int64_t, int64_t, int, int32_t *, void *,
                                 size_t, pico_stats *, hipStream_t, const int32_t *, int);
 
+// Workspace of a packed batch: the per-graph status words first (where
+// pico_batch_status finds them), then the working arrays.  PICO_ALGO_AUTO
+// holds HistoCore's arrays plus a second state and two more task tables.
 size_t batched_ws_bytes(int64_t G, int64_t total_n, int64_t total_m, int algo) {
-    size_t b = carve_bytes(total_n, 4) * 4 + carve_bytes(1, sizeof(BatchState)) +
+    const int a = algo & PICO_ALGO_MASK;
+    size_t b = carve_bytes(G, 4) + carve_bytes(total_n, 4) * 4 + carve_bytes(1, sizeof(BatchState)) +
                carve_bytes(G, sizeof(Task));
-    if ((algo & PICO_ALGO_MASK) == PICO_ALGO_HISTOCORE) b += carve_bytes(total_m, 4) + carve_bytes(total_n, 4);
+    if (a == PICO_ALGO_HISTOCORE || a == PICO_ALGO_AUTO) b += carve_bytes(total_m, 4) + carve_bytes(total_n, 4);
+    if (a == PICO_ALGO_AUTO) b += carve_bytes(1, sizeof(BatchState)) + carve_bytes(G, sizeof(Task)) * 2 + carve_bytes(G, 4);
     return b;
 }
 
@@ -1416,21 +1510,73 @@ int help_min_large(const pico_batch_tune *tune, int algo) {
 }
 
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo) {
+    const int a = algo & PICO_ALGO_MASK;
     long long words = 4 * task_al(n);
-    if ((algo & PICO_ALGO_MASK) == PICO_ALGO_HISTOCORE) words += task_al(n) + task_al(m);
+    if (a == PICO_ALGO_HISTOCORE || a == PICO_ALGO_AUTO) words += task_al(n) + task_al(m);
     return (size_t)words * 4;
 }
 
+// Task-list workspace: status words first, the task table, the host list's
+// device copy, the state; then what PICO_ALGO_AUTO adds (a second state, two
+// per-algorithm tables, the choices).
 size_t tasks_ws_bytes(int64_t T) {
-    return carve_bytes(T, sizeof(Task)) + carve_bytes(T, sizeof(pico_task)) +
-           carve_bytes(1, sizeof(BatchState));
+    return carve_bytes(T, 4) + carve_bytes(T, sizeof(Task)) + carve_bytes(T, sizeof(pico_task)) +
+           carve_bytes(1, sizeof(BatchState)) + carve_bytes(1, sizeof(BatchState)) +
+           carve_bytes(T, sizeof(Task)) * 2 + carve_bytes(T, 4);
 }
+
+namespace {
+
+void merge_stats(pico_batch_stats *into, const pico_batch_stats &x) {
+    into->iterations += x.iterations;
+    into->atomics += x.atomics;
+    into->frontier_total += x.frontier_total;
+    into->edges_scanned += x.edges_scanned;
+    into->buckets_scanned += x.buckets_scanned;
+    into->pushes += x.pushes;
+    into->lds_graphs += x.lds_graphs;
+    into->workgroups += x.workgroups;
+    into->helped_graphs += x.helped_graphs;
+    into->help_chunks += x.help_chunks;
+    into->histocore_graphs += x.histocore_graphs;
+}
+
+// PICO_ALGO_AUTO over a built task table `all`: choose per graph, split into
+// two tables with holes, one launch per algorithm on the stream (PeelOne
+// first).  With stats, each launch waits and the two are merged.
+int launch_auto(Task *all, Task *po, Task *hc, int32_t *choice, long long T, const pico_batch_tune *tune,
+                BatchState *st_po, BatchState *st_hc, int32_t *status, pico_batch_stats *stats,
+                hipStream_t stream, long long want) {
+    long long cb = T < 4096 ? T : 4096;
+    PICO_LAUNCH("choose_tasks", choose_tasks, dim3((unsigned)(cb > 0 ? cb : 1)), dim3(kBlock), stream, all, T,
+                choice, st_hc);
+    PICO_LAUNCH("split_tasks", split_tasks, dim3((unsigned)((T + 255) / 256)), dim3(256), stream, all, T, choice,
+                po, hc);
+    pico_batch_stats s_po, s_hc;
+    int rc = launch_tasks(po, T, PICO_ALGO_PEELONE, tune, st_po, status, stats ? &s_po : nullptr, stream, want);
+    if (rc) return rc;
+    long long chose = 0;
+    rc = launch_tasks(hc, T, PICO_ALGO_HISTOCORE, tune, st_hc, status, stats ? &s_hc : nullptr, stream, want,
+                      &chose);
+    if (rc) return rc;
+    if (stats) {
+        *stats = s_po;
+        merge_stats(stats, s_hc);
+        stats->graphs = T;
+        stats->histocore_graphs = chose;
+        if (s_hc.lds_bytes > stats->lds_bytes) stats->lds_bytes = s_hc.lds_bytes;
+    }
+    return PICO_OK;
+}
+
+}  // namespace
 
 int run_batched(const long long *vptr, const long long *off, const int32_t *cols, int64_t G,
                 int64_t total_n, int64_t total_m, int algo, const int32_t *order, int32_t *out,
                 void *ws, size_t ws_bytes, const pico_batch_tune *tune, pico_batch_stats *stats,
                 hipStream_t stream) {
     Carve cv{static_cast<char *>(ws), 0, ws_bytes};
+    int32_t *status = cv.take<int32_t>(G);
     PackedArrays p;
     p.vptr = vptr;
     p.off = off;
@@ -1444,48 +1590,69 @@ int run_batched(const long long *vptr, const long long *off, const int32_t *cols
     p.L2 = cv.take<int32_t>(total_n);
     p.histo = nullptr;
     p.oldcore = nullptr;
-    const bool hc = algo == PICO_ALGO_HISTOCORE;
+    const bool hc = algo == PICO_ALGO_HISTOCORE || algo == PICO_ALGO_AUTO;
     if (hc) {
         p.histo = cv.take<int32_t>(total_m);
         p.oldcore = cv.take<int32_t>(total_n);
     }
     BatchState *st = cv.take<BatchState>(1);
     Task *tasks = cv.take<Task>(G);
-    if (!p.core || !p.L0 || !p.L1 || !p.L2 || !st || !tasks ||
-        (hc && ((total_m > 0 && !p.histo) || !p.oldcore))) {
+    const bool aut = algo == PICO_ALGO_AUTO;
+    BatchState *st2 = aut ? cv.take<BatchState>(1) : nullptr;
+    Task *po = aut ? cv.take<Task>(G) : nullptr;
+    Task *hct = aut ? cv.take<Task>(G) : nullptr;
+    int32_t *choice = aut ? cv.take<int32_t>(G) : nullptr;
+    if (!status || !p.core || !p.L0 || !p.L1 || !p.L2 || !st || !tasks ||
+        (hc && ((total_m > 0 && !p.histo) || !p.oldcore)) || (aut && (!st2 || !po || !hct || !choice))) {
         set_error("batched workspace too small (%zu bytes given, %zu needed)", ws_bytes,
                   batched_ws_bytes(G, total_n, total_m, algo));
         return PICO_ENOMEM;
     }
     PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st);
+    if (aut) PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st2);
     PICO_LAUNCH("packed_tasks", packed_tasks, dim3((unsigned)((G + 255) / 256)), dim3(256), stream, p,
-                tasks, st);
+                tasks, st, status);
     // a packed batch fills the device: its tail is helped by whoever is idle
-    return launch_tasks(tasks, G, algo, tune, st, stats, stream, G > kMaxGrid ? G : kMaxGrid);
+    const long long want = G > kMaxGrid ? G : kMaxGrid;
+    if (aut) return launch_auto(tasks, po, hct, choice, G, tune, st, st2, status, stats, stream, want);
+    return launch_tasks(tasks, G, algo, tune, st, status, stats, stream, want);
 }
 
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,
                      const pico_batch_tune *tune, pico_batch_stats *stats, hipStream_t stream,
                      int64_t n_large) {
     Carve cv{static_cast<char *>(ws), 0, ws_bytes};
+    int32_t *status = cv.take<int32_t>(T);
     Task *tasks = cv.take<Task>(T);
     cv.take<pico_task>(T);
     BatchState *st = cv.take<BatchState>(1);
-    if (!tasks || !st) {
+    BatchState *st2 = cv.take<BatchState>(1);
+    Task *po = cv.take<Task>(T);
+    Task *hct = cv.take<Task>(T);
+    int32_t *choice = cv.take<int32_t>(T);
+    if (!status || !tasks || !st || !st2 || !po || !hct || !choice) {
         set_error("tasks workspace too small (%zu bytes given, %zu needed)", ws_bytes, tasks_ws_bytes(T));
         return PICO_ENOMEM;
     }
+    const bool aut = algo == PICO_ALGO_AUTO;
     PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st);
+    if (aut) PICO_LAUNCH("batch_state_init", batch_state_init, dim3(1), dim3(kBlock), stream, st2);
     PICO_LAUNCH("public_tasks", public_tasks, dim3((unsigned)((T + 255) / 256)), dim3(256), stream,
-                dev_tasks, (long long)T, algo == PICO_ALGO_HISTOCORE ? 1 : 0, tasks);
+                dev_tasks, (long long)T, algo == PICO_ALGO_PEELONE ? 0 : 1, tasks, status);
     // a few helpers per large task, so that a launch holding one large graph
     // leaves room on the device for the launches beside it
-    return launch_tasks(tasks, T, algo, tune, st, stats, stream, T + kHelpersPerBig * n_large);
+    const long long want = T + kHelpersPerBig * n_large;
+    if (aut) return launch_auto(tasks, po, hct, choice, T, tune, st, st2, status, stats, stream, want);
+    return launch_tasks(tasks, T, algo, tune, st, status, stats, stream, want);
 }
 
-// Device copy of a host task array inside the tasks workspace (second slot).
+// The status words at the start of a batched or task-list workspace.
+const int32_t *status_words(const void *ws) { return static_cast<const int32_t *>(ws); }
+
+// Device copy of a host task array inside the tasks workspace (third slot).
 pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T) {
     Carve cv{static_cast<char *>(ws), 0, ws_bytes};
+    cv.take<int32_t>(T);
     cv.take<Task>(T);
     return cv.take<pico_task>(T);
 }

@@ -685,6 +685,10 @@ int run_small(const Off *off, const int32_t *cols, int64_t n, int64_t m, int alg
 size_t task_scratch_bytes(int64_t n, int64_t m, int algo);
 size_t tasks_ws_bytes(int64_t T);
 pico_task *tasks_table(void *ws, size_t ws_bytes, int64_t T);
+// The per-graph status words at the start of a batched or task-list
+// workspace (PICO_EHIP until finished, then PICO_OK; PICO_EINVAL for an
+// invalid packed graph).
+const int32_t *status_words(const void *ws);
 // n_large: how many tasks will take helpers (help_min_large); the grid gets a
 // few extra workgroups for each.
 int run_tasks_device(const pico_task *dev_tasks, int64_t T, int algo, void *ws, size_t ws_bytes,

@@ -103,6 +103,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     pico_task *staging = nullptr;  // pinned host copy of the task table
+    int32_t *status = nullptr;     // pinned host copy of the launch's status words
     void *ws = nullptr;            // device tasks workspace
     size_t ws_bytes = 0;
     std::vector<Req> reqs;
@@ -136,6 +137,7 @@ void destroy_slots(pico_server *s) {
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.staging) (void)hipHostFree(sl.staging);
+        if (sl.status) (void)hipHostFree(sl.status);
         if (sl.ws) (void)hipFree(sl.ws);
     }
     s->slots.clear();
@@ -151,11 +153,15 @@ int reap(pico_server *s) {
             return PICO_EHIP;
         }
         const uint64_t t = now_ns();
-        for (Req &r : sl.reqs) {
+        for (size_t i = 0; i < sl.reqs.size(); ++i) {
+            Req &r = sl.reqs[i];
             s->arena.release(r.arena_off, r.bytes);
             pico_completion c;
             c.tag = r.r.tag;
-            c.status = PICO_OK;
+            // the launch's status word for this request (copied after the
+            // kernels, before the slot's event): PICO_OK, or PICO_EHIP if a
+            // wait bound left it unfinished
+            c.status = sl.status[i];
             c.reserved = 0;
             c.t_submit_ns = r.t_submit;
             c.t_launch_ns = r.t_launch;
@@ -226,6 +232,8 @@ int launch(pico_server *s, Slot &sl, int cls) {
     int rc = run_tasks_device(dev, T, algo, sl.ws, sl.ws_bytes, &s->cfg.tune, nullptr, sl.stream,
                               n_large);
     if (rc) return rc;
+    PICO_HIP_TRY(hipMemcpyAsync(sl.status, status_words(sl.ws), sizeof(int32_t) * T, hipMemcpyDeviceToHost,
+                                sl.stream));
     PICO_HIP_TRY(hipEventRecord(sl.done, sl.stream));
     sl.cls = cls;
     sl.busy = true;
@@ -246,7 +254,8 @@ int pico_server_create(const pico_server_config *cfg, pico_server **out) {
     }
     *out = nullptr;
     const int a = cfg->algo & PICO_ALGO_MASK;
-    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE) || (cfg->algo & ~PICO_ALGO_MASK) != 0) {
+    if ((a != PICO_ALGO_PEELONE && a != PICO_ALGO_HISTOCORE && a != PICO_ALGO_AUTO) ||
+        (cfg->algo & ~PICO_ALGO_MASK) != 0) {
         set_error("unknown algo %d", cfg->algo);
         return PICO_EINVAL;
     }
@@ -282,6 +291,8 @@ int pico_server_create(const pico_server_config *cfg, pico_server **out) {
         if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) break;
         if ((e = hipHostMalloc((void **)&sl.staging, sizeof(pico_task) * T, hipHostMallocDefault)) !=
             hipSuccess)
+            break;
+        if ((e = hipHostMalloc((void **)&sl.status, sizeof(int32_t) * T, hipHostMallocDefault)) != hipSuccess)
             break;
         if ((e = hipMalloc(&sl.ws, sl.ws_bytes)) != hipSuccess) break;
     }

@@ -107,7 +107,7 @@ def test_task_and_server_argument_checks_need_no_device():
         pico.pico_task_scratch_bytes(2**31, 0, pe)
     assert pico.pico_tasks_workspace_bytes(100) > 100 * ctypes.sizeof(pico.Task)
     assert ctypes.sizeof(pico.Task) == 56 and ctypes.sizeof(pico.BatchTune) == 16
-    assert ctypes.sizeof(pico.BatchStats) == 9 * 8 + 8 + 2 * 8
+    assert ctypes.sizeof(pico.BatchStats) == 9 * 8 + 8 + 3 * 8
     assert ctypes.sizeof(pico.Completion) == 40
     # bad task lists are rejected on the host, before any device work
     bad = pico.Task(None, None, -1, 0, None, None, 0)
@@ -151,3 +151,17 @@ def test_schedule_argument_errors_need_no_device():
     assert rc == pico.PICO_EINVAL and "schedule" in pico.pico_last_error()
     rc, _ = pico.pico_coreness_schedule(None, None, 0, 0, 0, None, None, 0, None, None, -1)
     assert rc == pico.PICO_EINVAL
+
+
+def test_batch_status_and_auto_sizes_need_no_device():
+    """pico_batch_status checks its arguments before touching the device;
+    PICO_ALGO_AUTO is accepted by the multi-graph size queries and sizes
+    scratch and workspace for HistoCore (plus the per-graph choice)."""
+    assert pico.pico_batch_status(None, 0, 0) == pico.PICO_OK
+    assert pico.pico_batch_status(None, 0, -1) == pico.PICO_EINVAL
+    assert pico.pico_batch_status(None, 0, 4) == pico.PICO_EINVAL
+    a, h, p = pico.PICO_ALGO_AUTO, pico.PICO_ALGO_HISTOCORE, pico.PICO_ALGO_PEELONE
+    assert pico.pico_task_scratch_bytes(1000, 9000, a) == pico.pico_task_scratch_bytes(1000, 9000, h)
+    assert pico.pico_task_scratch_bytes(1000, 9000, p) < pico.pico_task_scratch_bytes(1000, 9000, h)
+    assert pico.pico_batched_workspace_bytes(10, 1000, 9000, a) > pico.pico_batched_workspace_bytes(10, 1000, 9000, h)
+    assert pico.pico_tasks_workspace_bytes(10) > 0

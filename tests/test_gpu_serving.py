@@ -34,10 +34,10 @@ def _scratch(n, m, algo):
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
 
 
-@pytest.mark.parametrize("algo", ["peelone", "histocore"])
+@pytest.mark.parametrize("algo", ["peelone", "histocore", "auto"])
 def test_tasks_match_oracle(pool, algo):
     b, graphs = pool
-    code = pico.ALGOS[algo]
+    code = pico.BATCH_ALGOS[algo]
     keep, tasks = [], []
     order = sorted(range(len(graphs)), key=lambda i: -graphs[i]["n"])
     for i in order:
@@ -57,9 +57,11 @@ def test_tasks_match_oracle(pool, algo):
         g = graphs[i]
         assert np.array_equal(out[:g["n"]].cpu().numpy(), g["want"]), f"graph {i} n={g['n']}"
     assert st.graphs == len(tasks) and st.lds_graphs > 0 and st.lds_graphs < len(tasks)
+    rc, words = pico.batch_status(ws, len(tasks))
+    assert rc == pico.PICO_OK and (words == 0).all()
 
 
-@pytest.mark.parametrize("algo", ["peelone", "histocore"])
+@pytest.mark.parametrize("algo", ["peelone", "histocore", "auto"])
 def test_server_alone_vs_mix(pool, algo):
     """Requests arrive in bursts while earlier ones run; the arena admits only
     part of them at a time, up to three launches are in flight, and small
@@ -67,7 +69,7 @@ def test_server_alone_vs_mix(pool, algo):
     equals the graph's result alone (the plain single-graph call) and the
     oracle's."""
     b, graphs = pool
-    code = pico.ALGOS[algo]
+    code = pico.BATCH_ALGOS[algo]
     alone = []
     for g in graphs:
         if g["n"] == 0:
