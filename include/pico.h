@@ -44,7 +44,7 @@
  *                           CntCore / NbrCore 2)
  *   PICO_HC_REBUILD_PERMILLE HistoCore rounds whose frontier rows hold at least
  *                           this share of the m entries (in 1/1000; default
- *                           700, above 1000 never) rebuild the histograms
+ *                           640, above 1000 never) rebuild the histograms
  *                           instead of running UpdateHisto
  *   PICO_SMALL_MAX_EDGES    entry bound of the one-workgroup path (default
  *                           2^14; 0 = never)

@@ -51,12 +51,13 @@ constexpr int kInitCh = 1024;  // InitHisto: edges per heavy piece
 constexpr int kSumWave = 4096;  // SumHisto: one wave up to this value, a workgroup above
 // Rounds whose frontier rows hold at least this share of m (in 1/1000)
 // rebuild the histograms instead of running UpdateHisto.  Measured on
-// MI355X: a rebuild costs about one InitHisto pass (RMAT-26: 50 ms, RMAT-22:
-// 2.9 ms), an UpdateHisto round about 115 ps per histogram move, and moves
-// run at 0.25-0.47 of a round's frontier edges; rebuilding paid in the
-// rounds whose frontier rows held at least 0.7 of the entries (the first
-// five on both graphs) and lost in the next ones.
-constexpr int kRebuildPermille = 700;
+// MI355X: a rebuild costs about one InitHisto pass over the current values
+// (RMAT-26: 41 ms, RMAT-22: 1.9 ms), an UpdateHisto round about 115 ps per
+// histogram move, and moves run at 0.25-0.47 of a round's frontier edges;
+// rebuilding paid in the rounds whose frontier rows held at least 0.65 of
+// the entries (the first six or seven on RMAT-22 and RMAT-26) and lost in
+// the next ones.
+constexpr int kRebuildPermille = 640;
 
 // Cumulative counters.  FET packs (edges << 31) | slots of the frontier lists.
 enum { FET = 0, H_TAIL, HS_TAIL, N_MOVES, N_EDGES, N_BUCKETS };
@@ -148,6 +149,42 @@ __device__ __forceinline__ void wave_reverse_sum(const int32_t *seg, int top, in
 
 // ---------------------------------------------------------------- InitHisto
 
+// One wave counts entries [e0, e0 + d) of the adjacency into a histogram of
+// c buckets (bucket min(core[u], c)) and records each neighbour's value in
+// ndeg; four entries per lane in flight: their columns, then their values,
+// then the counts.  Buckets up to `cap` are counted in the LDS array `lds`,
+// higher ones (c > cap: hub rows at the start, valued by their degree) with
+// atomics on the row's histogram `hrow` in memory.
+template <typename Off>
+__device__ __forceinline__ void count_row_lds(const HcArgs<Off> &a, long long e0, int d, int c, int *lds,
+                                              int cap, int32_t *hrow) {
+    constexpr int kR = 4;
+    const int lane = lane_id();
+    for (int j0 = 0; j0 < d; j0 += kR * kWave) {
+        int x[kR];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int j = j0 + r * kWave + lane;
+            x[r] = j < d ? a.cols[e0 + j] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int j = j0 + r * kWave + lane;
+            x[r] = j < d ? a.core[x[r]] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int j = j0 + r * kWave + lane;
+            if (j < d) {
+                a.ndeg[e0 + j] = x[r];
+                const int b = min(max(x[r], 1), c);
+                if (b <= cap) atomicAdd(&lds[b - 1], 1);
+                else atomicAdd(&hrow[b - 1], 1);
+            }
+        }
+    }
+}
+
 // Builds every vertex's histogram from its neighbours' current values and
 // pushes {v : cnt(v) < core(v)} to frontier buffer `buf`.  At the start
 // (rebuild false) a vertex's value is its degree, or its given bound; in a
@@ -171,17 +208,27 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
         int d = valid && (a.warm || rebuild) ? (int)((long long)a.off[v + 1] - e0) : c;
         bool push = false;
         if (valid && d > 0 && d <= kSmall) {
-            // one lane owns v's segment: plain read-modify-write, no atomics
-            for (int j = 0; j < c; ++j) a.histo[e0 + j] = 0;
-            for (int j = 0; j < d; ++j) {
-                int u = a.cols[e0 + j];
-                int du = a.core[u];
-                a.ndeg[e0 + j] = du;
-                int b = min(max(du, 1), c);  // core[u] >= 1 on a symmetric graph
-                a.histo[e0 + b - 1] += 1;
+            // one lane owns v's segment: all its columns, then all their
+            // values, each group of loads in flight at once; the counts in
+            // the lane's own LDS slots (no atomics), written out once
+            int *h = lds + lane * (kSmall + 1);
+            for (int j = 0; j < c; ++j) h[j] = 0;
+            int x[kSmall];
+#pragma unroll
+            for (int j = 0; j < kSmall; ++j) x[j] = j < d ? a.cols[e0 + j] : 0;
+#pragma unroll
+            for (int j = 0; j < kSmall; ++j) x[j] = j < d ? a.core[x[j]] : 0;
+#pragma unroll
+            for (int j = 0; j < kSmall; ++j) {
+                if (j < d) {
+                    a.ndeg[e0 + j] = x[j];
+                    h[min(max(x[j], 1), c) - 1] += 1;  // core[u] >= 1 on a symmetric graph
+                }
             }
-            push = a.histo[e0 + c - 1] < c;
+            for (int j = 0; j < c; ++j) a.histo[e0 + j] = h[j];
+            push = h[c - 1] < c;
         }
+        wave_lds_sync();  // the lanes' slots are done before the rows below reuse them
         unsigned long long mm = __ballot(valid && d > kSmall && d <= kLdsCap);
         while (mm) {
             int l = __ffsll(mm) - 1;
@@ -190,12 +237,7 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
             long long ea = __shfl(e0, l);
             for (int j = lane; j < cc; j += kWave) lds[j] = 0;
             wave_lds_sync();
-            for (int j = lane; j < dd; j += kWave) {
-                int u = a.cols[ea + j];
-                int du = a.core[u];
-                a.ndeg[ea + j] = du;
-                atomicAdd(&lds[min(max(du, 1), cc) - 1], 1);
-            }
+            count_row_lds(a, ea, dd, cc, lds, cc, a.histo + ea);
             wave_lds_sync();
             for (int j = lane; j < cc; j += kWave) a.histo[ea + j] = lds[j];
             int top = lds[cc - 1];
@@ -231,10 +273,16 @@ __device__ void init_histo(const HcArgs<Off> &a, int *lds, int *lds_scan, long l
 }
 
 // Heavy InitHisto rows, piece by piece: zero (pass 0) or count (pass 1).
+// A piece's buckets up to kLdsCap are counted in the wave's LDS histogram
+// and added to the row with one atomic per non-empty bucket (in rebuild
+// rounds a hub's value, hence every bucket, is usually below kLdsCap; at the
+// start its value is its degree but most of its neighbours' are small); the
+// buckets above, one atomic per entry.
 template <typename Off>
 __device__ void init_heavy(const HcArgs<Off> &a, unsigned long long h0, unsigned long long h1,
-                           int pass) {
+                           int pass, int *lds) {
     const long long nw = (long long)gridDim.x * kWavesPerBlock;
+    const int lane = lane_id();
     for (long long p = (long long)h0 + wave_id_global(); p < (long long)h1; p += nw) {
         long long desc = a.H[p % a.hcap];
         int v = (int)(desc >> 32);
@@ -242,15 +290,19 @@ __device__ void init_heavy(const HcArgs<Off> &a, unsigned long long h0, unsigned
         long long vb = (long long)a.off[v], ve = (long long)a.off[v + 1];
         const int c = a.core[v];  // buckets (the degree unless started from bounds)
         long long e0 = vb + j * kInitCh, e1 = e0 + kInitCh < ve ? e0 + kInitCh : ve;
-        for (long long e = e0 + lane_id(); e < e1; e += kWave) {
-            if (pass == 0) {
-                a.histo[e] = 0;
-            } else {
-                int u = a.cols[e];
-                int du = a.core[u];
-                a.ndeg[e] = du;
-                atomicAdd(&a.histo[vb + min(max(du, 1), c) - 1], 1);
+        if (pass == 0) {
+            for (long long e = e0 + lane; e < e1; e += kWave) a.histo[e] = 0;
+        } else {
+            const int cap = c < kLdsCap ? c : kLdsCap;
+            for (int b = lane; b < cap; b += kWave) lds[b] = 0;
+            wave_lds_sync();
+            count_row_lds(a, e0, (int)(e1 - e0), c, lds, cap, a.histo + vb);
+            wave_lds_sync();
+            for (int b = lane; b < cap; b += kWave) {
+                const int x = lds[b];
+                if (x) atomicAdd(&a.histo[vb + b], x);
             }
+            wave_lds_sync();
         }
     }
 }
@@ -500,9 +552,9 @@ void hc_persistent(HcArgs<Off> a) {
         init_histo<Off>(a, U.hist[threadIdx.x >> 6], lds_scan, lds_scan_l, lds64, buf, rebuild);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return false;
         const unsigned long long h1 = snap[H_TAIL], hs1 = snap[HS_TAIL];
-        init_heavy<Off>(a, h0, h1, 0);
+        init_heavy<Off>(a, h0, h1, 0, U.hist[threadIdx.x >> 6]);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return false;
-        init_heavy<Off>(a, h0, h1, 1);
+        init_heavy<Off>(a, h0, h1, 1, U.hist[threadIdx.x >> 6]);
         if (!grid_sync<kSnap>(gs, nb, a.limit, snap, bar)) return false;
         init_heavy_check<Off>(a, hs0, hs1, buf);
         return grid_sync<kSnap>(gs, nb, a.limit, snap, bar);

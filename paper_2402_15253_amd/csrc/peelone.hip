@@ -56,7 +56,11 @@ namespace {
 
 constexpr int kLq = 2048;          // LDS continuation queue per workgroup
 constexpr int kLocalMax = 4096;    // an LDS batch is expanded locally up to this many edges
-constexpr int kTile = kBlock * 8;  // scan items per block step
+// Survivors per thread per scan step.  16 was measured too: 156 VGPRs
+// instead of 125, the same scan time and slower drains (RMAT-26 131 -> 134
+// ms, RMAT-22 19.1 -> 21.0 ms).
+constexpr int kScanR = 8;
+constexpr int kTile = kBlock * kScanR;  // scan items per block step
 
 // Ablations of Alg. 4 (the variants the paper measures against):
 //   kStatic   -- no dynamic frontier (Table IV): a decrement never claims;
@@ -302,7 +306,7 @@ __device__ void po_init(const PoArgs<Off> &a, unsigned long long *na_ctr, unsign
     for (long long tile = (long long)blockIdx.x * kTile; tile < a.n; tile += step) {
         unsigned sv = 0;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < kScanR; ++r) {
             long long i = tile + r * kBlock + threadIdx.x;
             if (i < a.n) {
                 int c = (int)(a.off[i + 1] - a.off[i]);
@@ -318,7 +322,7 @@ __device__ void po_init(const PoArgs<Off> &a, unsigned long long *na_ctr, unsign
         int ps = block_excl_scan(__popc(sv), ts, lds);
         unsigned long long bs = block_reserve(ts, na_ctr, lds64);
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
+        for (int r = 0; r < kScanR; ++r)
             if (sv >> r & 1u) a.A0[bs + ps++] = (int)(tile + r * kBlock + threadIdx.x);
     }
     int bm = block_min(lmin, lds);
@@ -343,11 +347,11 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
     int claimed = 0;
     const long long step = (long long)gridDim.x * kTile;
     for (long long tile = (long long)blockIdx.x * kTile; tile < nsrc; tile += step) {
-        int vv[8];
+        int vv[kScanR];
         unsigned fr = 0, sv = 0, cand = 0;
         long long dsum = 0;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < kScanR; ++r) {
             long long i = tile + r * kBlock + threadIdx.x;
             int v = -1, cv = -1;
             if (i < nsrc) {
@@ -362,7 +366,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
             if (cv == k || ((kMode == kStatic || kMode == kGpp) && v >= 0 && cv < k)) cand |= 1u << r;
         }
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < kScanR; ++r) {
             int v = vv[r];
             if ((cand >> r & 1u) && claim_vertex(c.out, v, k)) {
                 fr |= 1u << r;
@@ -373,7 +377,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
         int ps = block_excl_scan(__popc(sv), ts, lds);
         unsigned long long bs = block_reserve(ts, na_ctr, lds64);
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
+        for (int r = 0; r < kScanR; ++r)
             if (sv >> r & 1u) dst[bs + ps++] = vv[r];
         int tf = 0;
         long long te = 0;
@@ -387,7 +391,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
         if (local) {
             local_edges += te;
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
+            for (int r = 0; r < kScanR; ++r)
                 if (fr >> r & 1u) c.lq.buf[(tail + pf++) % kLq] = vv[r];
             __syncthreads();
             if (threadIdx.x == 0) *c.lq.tail = tail + tf;
@@ -402,7 +406,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
             const unsigned long long bq = old & kSlotMask;
             const long long be = (long long)(old >> kSlotBits);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
+            for (int r = 0; r < kScanR; ++r) {
                 if (fr >> r & 1u) {
                     int v = vv[r];
                     long long rs = (long long)a.off[v];
