@@ -477,14 +477,31 @@ __device__ __forceinline__ void hc_relax(const bool (&act0)[kEbR], const int (&u
     for (int r = 0; r < kEbR; ++r) {
         push[r] = false;
         if (mv[r]) {
-            if (ov[r] >= cu[r]) {
-                // v leaves u's top bucket: the only case whose old count matters
-                int c = atomicSub(&a.histo[hb[r] + cu[r]], 1);
-                push[r] = c == cu[r];
+            // v moves from bucket src = min(oldcore[v], core[u]) of u to bucket
+            // cv.  When the two are neighbours in one aligned 8-byte word (in
+            // the rounds after the rebuild rounds values fall by one per
+            // round, so every move is between neighbouring buckets, half of
+            // them so aligned), one 64-bit add of +1 to the low half and -1
+            // to the high half does both: the low count cannot carry out and
+            // the high one is >= 1 (v is counted there).  The old high half
+            // is the old count of src, which the crossing test needs.
+            const bool top = ov[r] >= cu[r];
+            const int src = top ? cu[r] : ov[r];
+            const long long lo = hb[r] + cv[r];  // bucket cv's position
+            if (src == cv[r] + 1 && (lo & 1) == 0) {
+                const unsigned long long old =
+                    atomicAdd(reinterpret_cast<unsigned long long *>(a.histo + lo), 0xffffffff00000001ull);
+                push[r] = top && (int)(old >> 32) == cu[r];
             } else {
-                atomicSub(&a.histo[hb[r] + ov[r]], 1);  // no return value needed
+                if (top) {
+                    // v leaves u's top bucket: the only case whose old count matters
+                    int c = atomicSub(&a.histo[hb[r] + cu[r]], 1);
+                    push[r] = c == cu[r];
+                } else {
+                    atomicSub(&a.histo[hb[r] + ov[r]], 1);  // no return value needed
+                }
+                atomicAdd(&a.histo[lo], 1);
             }
-            atomicAdd(&a.histo[hb[r] + cv[r]], 1);
             ++nmove;
         }
     }
