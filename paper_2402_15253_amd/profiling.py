@@ -11,6 +11,7 @@ Usage (each run writes CSV files under its -d directory):
 
   python -m paper_2402_15253_amd.profiling stats DIR
   python -m paper_2402_15253_amd.profiling traffic DIR_F DIR_W CONFIG
+  python -m paper_2402_15253_amd.profiling counters DIR   # any --pmc run
 
 The traffic summary scales each counter by what the same counter reads for
 the 1 GiB device-to-device copy that bench.py's --copy-calibration performs
@@ -142,7 +143,50 @@ def recorded_traffic(kernel: str, config: str) -> int | None:
     return None
 
 
+def counters(d: str) -> dict:
+    """{kernel short name: {counter: mean value per dispatch}} of a --pmc run
+    (every counter the run collected, decomposition kernels only)."""
+    acc = {}
+    with open(_find(d, "counter_collection.csv")) as f:
+        for row in csv.DictReader(f):
+            for k in KERNELS:
+                if k in row["Kernel_Name"]:
+                    key = (k, row["Counter_Name"])
+                    s, c = acc.get(key, (0.0, 0))
+                    acc[key] = (s + float(row["Counter_Value"]), c + 1)
+    out = {}
+    for (k, name), (s, c) in acc.items():
+        out.setdefault(k, {})[name] = s / c
+    return out
+
+
+def format_counters(c: dict, cus: int = 256) -> str:
+    """One line per kernel and counter, plus the derived figures the
+    collected counters allow: occupancy (SQ_WAVE_CYCLES over GRBM_GUI_ACTIVE,
+    as rocprofv3's OccupancyPercent with 32 wave slots per CU), LDS bank
+    conflicts per LDS access cycle, L2 hit rate, and atomic requests."""
+    lines = []
+    for k in sorted(c):
+        v = c[k]
+        for name in sorted(v):
+            lines.append(f"{k}: {name} {v[name]:.6g} source={source_hash(k)}")
+        if "SQ_WAVE_CYCLES" in v and v.get("GRBM_GUI_ACTIVE"):
+            occ = 400.0 * v["SQ_WAVE_CYCLES"] / v["GRBM_GUI_ACTIVE"] / cus / 32
+            lines.append(f"{k}: derived occupancy_percent {occ:.2f}")
+        if "SQ_LDS_BANK_CONFLICT" in v and v.get("SQ_LDS_IDX_ACTIVE"):
+            busy = v["SQ_LDS_IDX_ACTIVE"] - v["SQ_LDS_BANK_CONFLICT"]
+            if busy > 0:
+                lines.append(f"{k}: derived lds_bank_conflicts_per_access {v['SQ_LDS_BANK_CONFLICT'] / busy:.4f}")
+        if "TCC_HIT_sum" in v and "TCC_MISS_sum" in v and v["TCC_HIT_sum"] + v["TCC_MISS_sum"] > 0:
+            hit = v["TCC_HIT_sum"] / (v["TCC_HIT_sum"] + v["TCC_MISS_sum"])
+            lines.append(f"{k}: derived l2_hit_rate {hit:.4f}")
+    return "\n".join(lines)
+
+
 def main(argv):
+    if len(argv) >= 2 and argv[0] == "counters":
+        print(format_counters(counters(argv[1])))
+        return 0
     if len(argv) >= 2 and argv[0] == "stats":
         for k, (calls, avg, tot) in kernel_stats(argv[1]).items():
             print(f"{k}: calls {calls} avg_ms {avg:.4f} total_ms {tot:.3f} source={source_hash(k)}")

@@ -208,3 +208,25 @@ def test_tiny_wait_bound_reports_unfinished_graphs(algo, monkeypatch):
     for g in range(G):
         if words[g] == pico.PICO_OK:
             assert np.array_equal(got[vp[g]:vp[g + 1]], wants[g]), g
+
+
+def test_autotuned_launch_on_every_size_class(tmp_path, monkeypatch):
+    """The autotuner's chosen launch (timed afresh: the cache points to an
+    empty file) on a batch that reaches the largest size class -- graphs of
+    up to 200,000 vertices, above the LDS tier and above the helpers'
+    threshold -- against the oracle on every graph, for both algorithms and
+    the per-graph choice."""
+    from paper_2402_15253_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    b = gg.mixed_batch(48, 200, 200_000, seed=4096)
+    sizes = (b.vptr[1:] - b.vptr[:-1]).numpy()
+    assert sizes.max() > 65_536 and sizes.min() < 4096
+    want = np.concatenate(_per_graph_oracle(b))
+    d = b.to("cuda")
+    order = pico.largest_first(d.vptr)
+    for algo in ("peelone", "histocore", "auto"):
+        tune = autotune.tune_batched(d, algo, order=order, use_cache=True)
+        got, st = pico.coreness_batched(d, algo, tune=tune, order=order, with_stats=True)
+        print(f"{algo} tune={tune.as_dict()} stats={st}", flush=True)
+        assert np.array_equal(got.cpu().numpy(), want), algo
+        assert st["lds_graphs"] < b.num_graphs

@@ -172,3 +172,50 @@ def test_helped_tasks_repeatable(algo):
         assert st.helped_graphs == len(tasks) and st.help_chunks > 0
         for i in range(len(tasks)):
             assert np.array_equal(keep[i][0].cpu().numpy(), alone[i]), f"rep {rep} graph {i}"
+
+
+@pytest.mark.parametrize("algo", ["peelone", "auto"])
+def test_server_trace_every_class_against_oracle(algo):
+    """A trace of 600 requests over a pool whose graphs reach every size class
+    (below 16,384 vertices, below 131,072, above) with the library's class
+    bounds, helpers for the large ones and four launch slots: every request's
+    output is compared with the oracle, vertex by vertex, and every
+    completion reads PICO_OK."""
+    b = gg.mixed_batch(30, 300, 240_000, seed=2000, device="cuda")
+    graphs = []
+    for g in range(b.num_graphs):
+        x0, x1 = int(b.vptr[g]), int(b.vptr[g + 1])
+        off = b.offsets[x0:x1 + 1]
+        m = int(off[-1] - off[0]) if x1 > x0 else 0
+        cpu = b.graph(g)
+        graphs.append({"off": off, "n": x1 - x0, "m": m,
+                       "want": oracle.bz_coreness(cpu.offsets.cpu(), cpu.cols.cpu())})
+    sizes = np.array([g["n"] for g in graphs])
+    assert (sizes < 16384).any() and ((sizes >= 16384) & (sizes < 131072)).any() and (sizes >= 131072).any()
+    code = pico.BATCH_ALGOS[algo]
+    need = sum(pico.pico_task_scratch_bytes(g["n"], g["m"], code) for g in graphs)
+    srv = pico.Server(algo, arena_bytes=max(need, 1 << 20), max_inflight=4, max_tasks_per_launch=64)
+    rng = np.random.default_rng(11)
+    R = 600
+    pick = rng.integers(0, len(graphs), R)
+    base = np.concatenate([[0], np.cumsum(sizes[pick])])
+    out = torch.full((int(base[-1]) + 1,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    done, r = 0, 0
+    while done < R:
+        for _ in range(int(rng.integers(1, 16))):
+            if r == R:
+                break
+            g = graphs[pick[r]]
+            srv.submit_ptrs(g["off"].data_ptr(), b.cols.data_ptr(), g["n"], g["m"],
+                            out.data_ptr() + 4 * int(base[r]), r)
+            r += 1
+        for c in srv.progress():
+            assert c.status == pico.PICO_OK, c.tag
+            done += 1
+    st = srv.status()
+    srv.close()
+    print(f"{algo}: {st}", flush=True)
+    got = out.cpu().numpy()
+    for i in range(R):
+        assert np.array_equal(got[base[i]:base[i + 1]], graphs[pick[i]]["want"]), f"request {i} graph {pick[i]}"
