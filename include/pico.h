@@ -33,22 +33,33 @@
  * different host threads if each uses its own workspace.
  *
  * Test and development overrides (environment variables; unset in
- * production, where the library picks launch shapes itself).  All but the
- * last are read at each call and must be positive integers (anything else
- * is ignored); PICO_SMALL_MAX_EDGES is read once per process, >= 0:
+ * production, where the library picks launch shapes itself).  They are read
+ * at each call and must be positive integers (anything else is ignored),
+ * except where marked >= 0; PICO_SMALL_MAX_EDGES is read once per process:
  *   PICO_GRID_BLOCKS        workgroups of a grid-wide persistent launch
  *                           (capped at what is co-resident)
  *   PICO_PO_BLOCKS_PER_CU   PeelOne workgroups per compute unit (default 1,
  *                           2 from 2^28 entries)
  *   PICO_HC_BLOCKS_PER_CU   HistoCore workgroups per compute unit (default 4;
  *                           CntCore / NbrCore 2)
+ *   PICO_PO_LOCAL_EDGES     PeelOne: a batch of vertices asserted within a
+ *                           workgroup is expanded by that workgroup when its
+ *                           rows hold at most this many edges (default 4096;
+ *                           0 sends every asserted vertex to the shared
+ *                           frontier of the next round); >= 0
  *   PICO_HC_REBUILD_PERMILLE HistoCore rounds whose frontier rows hold at least
  *                           this share of the m entries (in 1/1000; default
  *                           640, above 1000 never) rebuild the histograms
  *                           instead of running UpdateHisto
+ *   PICO_BATCH_WAIT_US      bound, in microseconds, on each wait of the
+ *                           multi-graph kernels for a graph's leader or
+ *                           helpers (default one minute); a graph whose wait
+ *                           runs out is left unfinished and its status word
+ *                           stays PICO_EHIP
  *   PICO_SMALL_MAX_EDGES    entry bound of the one-workgroup path (default
  *                           2^14; 0 = never)
- * They change only the launch shape or the work, never the result.
+ * All but PICO_BATCH_WAIT_US change only the launch shape or the work, never
+ * the result.
  */
 #ifndef PICO_H
 #define PICO_H

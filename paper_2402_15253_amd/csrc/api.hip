@@ -90,6 +90,13 @@ int tune_int(const char *name, int dflt) {
     return x > 0 ? x : dflt;
 }
 
+int tune_int_nonneg(const char *name, int dflt) {
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    int x = atoi(v);
+    return x >= 0 ? x : dflt;
+}
+
 unsigned long long wall_ticks(double seconds) {
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

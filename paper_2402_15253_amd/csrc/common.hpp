@@ -438,14 +438,21 @@ __device__ __forceinline__ void edge_balanced(const int32_t *__restrict__ ids,
     const long long lo = e_lo + span * (long long)blockIdx.x / (long long)gridDim.x;
     const long long hi = e_lo + span * (long long)(blockIdx.x + 1) / (long long)gridDim.x;
     if (lo >= hi) return;  // uniform across the workgroup
-    if (threadIdx.x == 0) {
-        long long a = q0, b = q1;  // largest i in [q0, q1) with es[i] <= lo
+    {
+        // largest i in [q0, q1) with es[i] <= lo, by the whole workgroup: each
+        // pass reads kBlock evenly spaced entries of the bracket [a, b) at once
+        // and keeps the gap between the last sample <= lo and the next one, so
+        // a list of up to 2^24 entries takes three dependent reads, not 24
+        long long a = q0, b = q1;
         while (b - a > 1) {
-            long long mid = (a + b) >> 1;
-            if (es[mid] <= lo) a = mid;
-            else b = mid;
+            const long long span = b - a;
+            const long long p = a + span * (long long)threadIdx.x / kBlock;
+            const int below = __syncthreads_count(es[p] <= lo);  // samples <= lo: a prefix, sample 0 is a
+            const long long na = a + span * (long long)(below - 1) / kBlock;
+            if (below < kBlock) b = a + span * (long long)below / kBlock;
+            a = na;
         }
-        L.next = a;
+        if (threadIdx.x == 0) L.next = a;
     }
     __syncthreads();
     // Window size: about twice the entries one step of kEbWin edges covers at
@@ -636,6 +643,8 @@ unsigned long long wall_ticks(double seconds);
 
 // Integer tuning knob read once from the environment (default if unset).
 int tune_int(const char *name, int dflt);
+// The same for knobs where 0 is meaningful (default if unset or negative).
+int tune_int_nonneg(const char *name, int dflt);
 
 // Optional per-launch HIP-event timing (pico_profile_enable).  prof_begin
 // returns a record index, or -1 when profiling is off on this host thread.

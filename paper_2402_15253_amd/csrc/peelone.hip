@@ -55,7 +55,7 @@ namespace pico {
 namespace {
 
 constexpr int kLq = 2048;          // LDS continuation queue per workgroup
-constexpr int kLocalMax = 4096;    // an LDS batch is expanded locally up to this many edges
+constexpr int kLocalMax = 4096;    // an LDS batch is expanded locally up to this many edges (default)
 // Survivors per thread per scan step.  16 was measured too: 156 VGPRs
 // instead of 125, the same scan time and slower drains (RMAT-26 131 -> 134
 // ms, RMAT-22 19.1 -> 21.0 ms).
@@ -119,6 +119,7 @@ struct PoArgs {
     long long sched_cap;
     double ns_per_tick;        // device wall clock period
     int mode;                  // kDynamic, or an ablation: kStatic, kRollback
+    int local_max;             // LDS batches up to this many edges are expanded locally
 };
 
 __global__ void po_state_init(PoState *st) {
@@ -260,7 +261,7 @@ __device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kE
 
 // Expand the workgroup's LDS queue until it is empty: a batch of up to 256
 // queued vertices at a time, expanded here when its rows hold at most
-// kLocalMax edges, otherwise sent to the global list for the next round.
+// local_max edges, otherwise sent to the global list for the next round.
 template <typename Off, int kMode>
 __device__ void drain_lds(const PoArgs<Off> &a, PoCtx<Off> &c, ExpandLds &X) {
     while (true) {
@@ -283,7 +284,7 @@ __device__ void drain_lds(const PoArgs<Off> &a, PoCtx<Off> &c, ExpandLds &X) {
         }
         long long tot = 0;
         (void)block_excl_scan64(d, tot, X.scan_l);
-        if (tot > kLocalMax) {
+        if (tot > a.local_max) {
             push_global(v >= 0, v, c);  // a burst: share it out next round
         } else {
             block_expand<kEbR>((int)d, rs, 0, 0, a.cols, X,
@@ -386,7 +387,7 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
         if (tf == 0) continue;
         claimed += tf;
         const unsigned tail = *c.lq.tail, keep = *c.lq.keep;
-        const bool local = kMode != kStatic && kMode != kGpp && local_edges + te <= kLocalMax &&
+        const bool local = kMode != kStatic && kMode != kGpp && local_edges + te <= a.local_max &&
                            tail + tf - keep <= (unsigned)kLq;
         if (local) {
             local_edges += te;
@@ -602,6 +603,7 @@ int run_peelone(const Off *off, const int32_t *cols, int64_t n, int64_t m, int32
     a.sched_cap = sched ? sched_cap : 0;
     a.ns_per_tick = 1e9 / (double)wall_ticks(1.0);
     a.mode = mode;
+    a.local_max = tune_int_nonneg("PICO_PO_LOCAL_EDGES", kLocalMax);
     int blocks = 0;
     // One workgroup per CU keeps the grid barriers cheap, which decides small
     // graphs (RMAT-22: 21.4 ms at one, 23.1 at two); on graphs with billions

@@ -186,6 +186,23 @@ def _check_histocore_rounds(st, steps, per_round, m):
     assert (steps[:, 4] == 1).all()
 
 
+@pytest.mark.parametrize("local_edges", ["0", "1", "300", "100000"])
+def test_peelone_local_expansion_bound(local_edges, monkeypatch):
+    """PeelOne's bound on workgroup-local expansion (PICO_PO_LOCAL_EDGES; 0:
+    every asserted vertex waits for the next shared round) moves work between
+    the LDS continuation queue and the global rounds, never the result: the
+    coreness and the level-by-level schedule equal BZ's."""
+    monkeypatch.setenv("PICO_PO_LOCAL_EDGES", local_edges)
+    g = gg.scaled_rmat_block(14, 7, 300, 0.6, 40)
+    print(f"case {g.name} n={g.n} m={g.m} local_edges={local_edges}", flush=True)
+    want = oracle.bz_coreness(g.offsets, g.cols)
+    core, st, steps = _schedule(g, "peelone")
+    assert np.array_equal(core, want)
+    _check_peelone_levels(want, st, steps)
+    if local_edges == "0":
+        assert st["sub_rounds"] > 0  # the asserted vertices went through shared rounds
+
+
 @pytest.mark.parametrize("make", [lambda: gg.er_10k(), lambda: gg.rmat(13, 16, 8),
                                   lambda: gg.scaled_rmat_block(14, 7, 300, 0.6, 40),
                                   lambda: gg.disjoint_union(gg.complete(30), gg.cycle(50), gg.empty_graph(4))])
