@@ -186,9 +186,11 @@ def random_access_roof(pico, st: dict, n: int, m: int, per_kernel: dict, ops: in
     arrays of the sizes they touch: the per-vertex value array (4n bytes)
     and HistoCore's histogram (4m bytes).  PeelOne gathers one neighbour
     value per adjacency entry and makes one atomic per decrement; HistoCore
-    makes two atomics per histogram move.  `frac` is that cost over the
-    measured launch time (1.0 = the launch does nothing but those accesses at
-    the probe's rate)."""
+    gathers one neighbour value per adjacency entry in InitHisto and in each
+    round that rebuilds the histograms, and makes two atomics per histogram
+    move (UpdateHisto's own value gathers, behind the neighbour-value bound,
+    are left out).  `frac` is that cost over the measured launch time (1.0 =
+    the launch does nothing but those accesses at the probe's rates)."""
     vals = pico.probe_random_access(4 * n, ops)
     hist = pico.probe_random_access(4 * m, ops)
     out = {"probe": {"values": vals, "histogram": hist}}
@@ -200,9 +202,10 @@ def random_access_roof(pico, st: dict, n: int, m: int, per_kernel: dict, ops: in
                                 "avg_launch_ms": avg, "frac": round(t / avg, 4)}
     if "hc_persistent" in per_kernel and "histocore" in st:
         moves = int(st["histocore"]["atomics"])
-        t = 2 * moves / hist["atomics_per_s"] * 1e3
+        gathers = (1 + int(st["histocore"].get("scans", 0))) * m  # InitHisto and rebuild rounds
+        t = (gathers / vals["gathers_per_s"] + 2 * moves / hist["atomics_per_s"]) * 1e3
         avg = per_kernel["hc_persistent"]["avg_ms"]
-        out["hc_persistent"] = {"atomics": 2 * moves, "ms_at_probe_rates": round(t, 3),
+        out["hc_persistent"] = {"gathers": gathers, "atomics": 2 * moves, "ms_at_probe_rates": round(t, 3),
                                 "avg_launch_ms": avg, "frac": round(t / avg, 4)}
     return out
 

@@ -160,14 +160,18 @@ typedef struct pico_stats {
                                (two atomic RMWs each) */
     int64_t buckets_scanned;/* HistoCore: histogram buckets read by SumHisto */
     int64_t pushes_dynamic; /* PeelOne: vertices asserted by the scatter (the
-                               dynamic frontier) rather than found by a scan;
+                               dynamic frontier) rather than found by a scan
+                               (on the grid path a vertex valued k when level k
+                               starts may be claimed by a decrement before the
+                               level's scan reaches it, so this split varies
+                               between runs; the level's total does not);
                                HistoCore: frontier entries pushed by UpdateHisto */
     double phase_ms[8];     /* device wall time by phase, barrier waits included.
                                PeelOne: [0] initialisation, [1] level scans,
                                [2] level drains.  HistoCore: [0] core = deg,
                                [1] InitHisto, [2] SumHisto, [3] SumHisto of
-                               large values, [4] UpdateHisto, [5] UpdateHisto
-                               of long rows. */
+                               large values, [4] UpdateHisto, [5] rounds that
+                               rebuilt the histograms instead. */
 } pico_stats;
 
 /* One step of a decomposition's schedule (pico_coreness_schedule): a level

@@ -27,7 +27,10 @@
 // k + 1 (it lowered v to k) or k (a stale filter read let it lower a
 // not-yet-claimed level-k vertex below k).  Every vertex whose value reaches
 // k or less during level k meets one of these, so none is lost, and the
-// compare-and-swap lets only one expand it.
+// compare-and-swap lets only one expand it.  Once the level's scan phase
+// has ended (a grid barrier), every vertex valued k or less is claimed, so in
+// the level's rounds the one decrement whose fetch returns k + 1 claims its
+// vertex alone, with a plain store.
 //
 // Dynamic frontier (Section III-C, step 3).  An asserted vertex is processed
 // in the same level.  While the work it brings is small, the workgroup that
@@ -37,6 +40,17 @@
 // barrier later.  The level ends at the first barrier after which the global
 // list has nothing new.  A level whose scan finds nobody jumps k straight to
 // the smallest surviving value.
+//
+// Local links.  A peel cascade followed through the LDS queue is a chain of
+// dependent memory round trips per link, so each link takes as few as it
+// can: the claim's compare-and-swap is issued together with the loads of the
+// claimed vertex's row bounds, which travel in the queue beside its id, and
+// a batch expanded locally decrements every neighbour without first reading
+// its value (a neighbour already peeled holds a value below k, so the fetch
+// returns less than k and claims nothing; every entry still decrements at
+// most once).  The edge-balanced rounds keep the filter read: they are
+// bound by throughput, and the read spares a memory-side atomic for every
+// peeled neighbour.
 //
 // Edge balance.  Each global frontier entry records where its adjacency row
 // starts in the concatenation of the round's rows, reserved together with the
@@ -135,6 +149,8 @@ __global__ void po_state_init(PoState *st) {
 // (entries are consumed in workgroup-wide batches).
 struct LdsQueue {
     int *buf;
+    long long *rs;  // each entry's first CSR position
+    int *d;         // ... and its row length
     unsigned *take;
     unsigned *tail;
     unsigned *keep;
@@ -154,19 +170,16 @@ struct PoCtx {
     int natom;
     int ndyn;
     int mode;
+    bool scanning;  // the level's scan phase: scanners claim too, so claims need a compare-and-swap
 };
 
 // Append the lanes' vertices to the global frontier list (one atomic per
 // wave), with their row starts in the concatenated edge space.
 template <typename Off>
-__device__ __forceinline__ void push_global(bool pred, int u, PoCtx<Off> &c) {
+__device__ __forceinline__ void push_global(bool pred, int u, long long rs, long long d, PoCtx<Off> &c) {
     unsigned long long mask = __ballot(pred);
     if (mask == 0ull) return;
-    long long rs = 0, d = 0;
-    if (pred) {
-        rs = (long long)c.off[u];
-        d = (long long)c.off[u + 1] - rs;
-    }
+    if (!pred) rs = d = 0;
     long long dpre = wave_incl_scan64(d) - d;
     long long dtot = __shfl(dpre + d, kWave - 1);
     const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -185,7 +198,7 @@ __device__ __forceinline__ void push_global(bool pred, int u, PoCtx<Off> &c) {
 // Assert the lanes' vertices into the level's frontier: the workgroup's LDS
 // queue while it has room, else the global list for the next round.
 template <typename Off>
-__device__ __forceinline__ void enqueue(bool pred, int u, PoCtx<Off> &c) {
+__device__ __forceinline__ void enqueue(bool pred, int u, long long rs, int d, PoCtx<Off> &c) {
     unsigned long long mask = __ballot(pred);
     if (mask == 0ull) return;
     const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -209,9 +222,12 @@ __device__ __forceinline__ void enqueue(bool pred, int u, PoCtx<Off> &c) {
     base = __shfl(base, leader);
     c.ndyn += pred ? 1 : 0;
     if (global) {
-        push_global(pred, u, c);
+        push_global(pred, u, rs, (long long)d, c);
     } else if (pred) {
-        c.lq.buf[(base + lane_rank(mask)) % kLq] = u;
+        const unsigned i = (base + lane_rank(mask)) % kLq;
+        c.lq.buf[i] = u;
+        c.lq.rs[i] = rs;
+        c.lq.d[i] = d;
     }
 }
 
@@ -224,12 +240,19 @@ __device__ __forceinline__ bool claim_vertex(int32_t *out, int v, int k) {
 // kMode: the variant this kernel is compiled for (each its own kernel, so
 // Alg. 4's carries none of the ablations' code).
 template <typename Off, int kMode>
-__device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kEbR], PoCtx<Off> &c) {
+__device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kEbR], PoCtx<Off> &c,
+                                      bool filter = true) {
     constexpr int mode = kMode;
     const bool gpp = mode == kGpp;
     int cu[kEbR];
+    if (mode == kDynamic && !filter) {
+        // a local batch: every neighbour is decremented, without the filter read
 #pragma unroll
-    for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? (gpp ? c.out[u[r]] : c.core[u[r]]) : 0;
+        for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? INT_MAX : 0;
+    } else {
+#pragma unroll
+        for (int r = 0; r < kEbR; ++r) cu[r] = act[r] ? (gpp ? c.out[u[r]] : c.core[u[r]]) : 0;
+    }
     int old[kEbR];
 #pragma unroll
     for (int r = 0; r < kEbR; ++r) {
@@ -249,14 +272,36 @@ __device__ __forceinline__ void relax(const bool (&act)[kEbR], const int (&u)[kE
             }
         }
     }
-    bool push[kEbR];
+    int got[kEbR];
+    long long rs[kEbR], re[kEbR];
+    if (mode == kDynamic && !c.scanning) {
+        // after the level's scan every vertex at or below k is claimed, so the
+        // one decrement that takes u from k + 1 to k claims it alone
 #pragma unroll
-    for (int r = 0; r < kEbR; ++r) {
-        push[r] = act[r] && cu[r] > c.k && (old[r] == c.k + 1 || old[r] == c.k) &&
-                  claim_vertex(c.out, u[r], c.k);
+        for (int r = 0; r < kEbR; ++r) {
+            got[r] = act[r] && cu[r] > c.k && old[r] == c.k + 1 ? 1 : 0;
+            rs[r] = re[r] = 0;
+            if (got[r]) {
+                c.out[u[r]] = c.k;
+                rs[r] = (long long)c.off[u[r]];
+                re[r] = (long long)c.off[u[r] + 1];
+            }
+        }
+    } else {
+        // a candidate's claim and its row bounds in one round trip
+#pragma unroll
+        for (int r = 0; r < kEbR; ++r) {
+            got[r] = 0;
+            rs[r] = re[r] = 0;
+            if (act[r] && cu[r] > c.k && (old[r] == c.k + 1 || old[r] == c.k)) {
+                got[r] = atomicCAS(&c.out[u[r]], -1, c.k) == -1 ? 1 : 0;
+                rs[r] = (long long)c.off[u[r]];
+                re[r] = (long long)c.off[u[r] + 1];
+            }
+        }
     }
 #pragma unroll
-    for (int r = 0; r < kEbR; ++r) enqueue(push[r], u[r], c);
+    for (int r = 0; r < kEbR; ++r) enqueue(got[r] != 0, u[r], rs[r], (int)(re[r] - rs[r]), c);
 }
 
 // Expand the workgroup's LDS queue until it is empty: a batch of up to 256
@@ -278,18 +323,19 @@ __device__ void drain_lds(const PoArgs<Off> &a, PoCtx<Off> &c, ExpandLds &X) {
         int v = -1;
         long long rs = 0, d = 0;
         if (threadIdx.x < cnt) {
-            v = c.lq.buf[(tk + threadIdx.x) % kLq];
-            rs = (long long)a.off[v];
-            d = (long long)a.off[v + 1] - rs;
+            const unsigned i = (tk + threadIdx.x) % kLq;
+            v = c.lq.buf[i];
+            rs = c.lq.rs[i];
+            d = c.lq.d[i];
         }
         long long tot = 0;
         (void)block_excl_scan64(d, tot, X.scan_l);
         if (tot > a.local_max) {
-            push_global(v >= 0, v, c);  // a burst: share it out next round
+            push_global(v >= 0, v, rs, d, c);  // a burst: share it out next round
         } else {
             block_expand<kEbR>((int)d, rs, 0, 0, a.cols, X,
                                [&](const bool (&act)[kEbR], const int (&u)[kEbR], const int (&)[kEbR]) {
-                                   relax<Off, kMode>(act, u, c);
+                                   relax<Off, kMode>(act, u, c, false);
                                });
         }
         __syncthreads();
@@ -349,6 +395,8 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
     const long long step = (long long)gridDim.x * kTile;
     for (long long tile = (long long)blockIdx.x * kTile; tile < nsrc; tile += step) {
         int vv[kScanR];
+        long long vrs[kScanR];
+        int vd[kScanR];
         unsigned fr = 0, sv = 0, cand = 0;
         long long dsum = 0;
 #pragma unroll
@@ -369,9 +417,13 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
 #pragma unroll
         for (int r = 0; r < kScanR; ++r) {
             int v = vv[r];
+            vrs[r] = 0;
+            vd[r] = 0;
             if ((cand >> r & 1u) && claim_vertex(c.out, v, k)) {
                 fr |= 1u << r;
-                dsum += (long long)(a.off[v + 1] - a.off[v]);
+                vrs[r] = (long long)a.off[v];
+                vd[r] = (int)((long long)a.off[v + 1] - vrs[r]);
+                dsum += vd[r];
             }
         }
         int ts = 0;
@@ -393,7 +445,12 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
             local_edges += te;
 #pragma unroll
             for (int r = 0; r < kScanR; ++r)
-                if (fr >> r & 1u) c.lq.buf[(tail + pf++) % kLq] = vv[r];
+                if (fr >> r & 1u) {
+                    const unsigned i = (tail + pf++) % kLq;
+                    c.lq.buf[i] = vv[r];
+                    c.lq.rs[i] = vrs[r];
+                    c.lq.d[i] = vd[r];
+                }
             __syncthreads();
             if (threadIdx.x == 0) *c.lq.tail = tail + tf;
             __syncthreads();
@@ -409,13 +466,11 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
 #pragma unroll
             for (int r = 0; r < kScanR; ++r) {
                 if (fr >> r & 1u) {
-                    int v = vv[r];
-                    long long rs = (long long)a.off[v];
-                    a.Q[bq + pf] = v;
+                    a.Q[bq + pf] = vv[r];
                     a.QE[bq + pf] = be + pe;
-                    a.QR[bq + pf] = rs;
+                    a.QR[bq + pf] = vrs[r];
                     ++pf;
-                    pe += (long long)a.off[v + 1] - rs;
+                    pe += vd[r];
                 }
             }
         }
@@ -448,6 +503,8 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     __shared__ unsigned long long lds64[1];
     __shared__ unsigned long long snap[kNumCtr + 1];
     __shared__ int lq_buf[kLq];
+    __shared__ long long lq_rs[kLq];
+    __shared__ int lq_d[kLq];
     __shared__ unsigned lq_take, lq_tail, lq_keep;
     __shared__ EbLds eb;
     __shared__ ExpandLds xl;
@@ -457,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
     unsigned long long bar = 0;
     if (threadIdx.x == 0) lq_take = lq_tail = lq_keep = 0;
     PoCtx<Off> c{a.off, a.core, a.out, a.Q, a.QE, a.QR, &gs->ctr[QET].v,
-                 LdsQueue{lq_buf, &lq_take, &lq_tail, &lq_keep}, 0, 0, 0, mode};
+                 LdsQueue{lq_buf, lq_rs, lq_d, &lq_take, &lq_tail, &lq_keep}, 0, 0, 0, mode, true};
 
     const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
     PhaseClock clk;
@@ -497,6 +554,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
             st_rlx(&st->nf[(j + 1) % 3].v, 0ull);
             st_rlx(&st->dynl[(j + 1) % 3].v, 0ull);
         }
+        c.scanning = true;
         po_scan<Off, kMode>(a, c, src, nprev, dst, &st->na[j % 3].v, &st->mn[j % 3].v, &st->nf[j % 3].v,
                      lds, lds_l, lds64);
         drain_lds<Off, kMode>(a, c, xl);
@@ -523,6 +581,7 @@ __global__ __launch_bounds__(kBlock) void po_persistent(PoArgs<Off> a) {
         const long long rounds_before = rounds;
         unsigned long long q0 = q_end, e0 = e_end;
         unsigned long long q1 = snap[QET] & kSlotMask, e1 = snap[QET] >> kSlotBits;
+        c.scanning = false;
         while (q0 < q1) {
             po_round<Off, kMode>(a, c, q0, q1, e0, e1, eb, xl);
             ++rounds;

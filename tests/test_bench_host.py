@@ -26,7 +26,7 @@ class FakeProbe:
 def test_random_access_roof_arithmetic():
     n, m = 1000, 8000
     fake = FakeProbe({4 * n: (80e9, 25e9), 4 * m: (50e9, 20e9)})
-    st = {"peelone": {"atomics": 3000}, "histocore": {"atomics": 5000}}
+    st = {"peelone": {"atomics": 3000}, "histocore": {"atomics": 5000, "scans": 2}}
     per_kernel = {"po_persistent": {"avg_ms": 0.5}, "hc_persistent": {"avg_ms": 2.0}}
     r = bench.random_access_roof(fake, st, n, m, per_kernel, ops=1 << 10)
     assert fake.calls == [4 * n, 4 * m]
@@ -36,8 +36,10 @@ def test_random_access_roof_arithmetic():
     assert abs(po["ms_at_probe_rates"] - round(want_po, 3)) < 1e-9
     assert abs(po["frac"] - round(want_po / 0.5, 4)) < 1e-9
     hc = r["hc_persistent"]
-    want_hc = 2 * 5000 / 20e9 * 1e3  # two atomics per histogram move, histogram-sized array
-    assert hc["atomics"] == 10000
+    # a value gather per entry in InitHisto and in each of the 2 rebuild rounds
+    # (value-array rates), two atomics per histogram move (histogram-sized array)
+    want_hc = (3 * m / 80e9 + 2 * 5000 / 20e9) * 1e3
+    assert hc["atomics"] == 10000 and hc["gathers"] == 3 * m
     assert abs(hc["frac"] - round(want_hc / 2.0, 4)) < 1e-9
 
 

@@ -86,19 +86,22 @@ def test_large_clique_one_workgroup(algo):
 @pytest.mark.parametrize("offsets_dtype", [torch.int32, torch.int64])
 def test_paths_agree_on_schedule(offsets_dtype, monkeypatch):
     """The one-workgroup and grid paths report the same schedule where it is
-    fixed by the graph: PeelOne's levels, peeled and asserted vertices and
-    k_max; HistoCore's rounds, frontier sizes, edges scanned and histogram
-    moves (Theorem 2 fixes the synchronous rounds).  Scan counts may differ
-    by one: the grid path ends with a scan that finds no survivor when the
-    last level's survivors were all asserted during its drain.  The grid
-    path's histogram rebuild rounds are switched off here (they read every
-    entry and move nothing); test_rebuild_rounds_keep_the_schedule covers
-    them."""
+    fixed by the graph: PeelOne's levels, peeled vertices and k_max;
+    HistoCore's rounds, frontier sizes, edges scanned and histogram moves
+    (Theorem 2 fixes the synchronous rounds).  PeelOne's split of each level
+    between vertices its scan found and vertices a decrement asserted is not
+    fixed on the grid path (a workgroup's local batch may decrement and claim
+    a vertex valued k before another workgroup's scan reaches it), so only
+    its bounds are checked; the per-level totals are compared element by
+    element in the schedule tests.  Scan counts may differ by one: the grid
+    path ends with a scan that finds no survivor when the last level's
+    survivors were all asserted during its drain.  The grid path's histogram
+    rebuild rounds are switched off here (they read every entry and move
+    nothing); test_rebuild_rounds_keep_the_schedule covers them."""
     monkeypatch.setenv("PICO_HC_REBUILD_PERMILLE", "2000")
     g = gg.rmat(13, 16, 21).with_offsets(offsets_dtype)
     print(f"case {g.name} n={g.n} m={g.m} {offsets_dtype}", flush=True)
-    for algo, keys in (("peelone", ("iterations", "frontier_total", "k_max", "pushes_dynamic",
-                                    "edges_scanned")),
+    for algo, keys in (("peelone", ("iterations", "frontier_total", "k_max", "edges_scanned")),
                        ("histocore", ("iterations", "frontier_total", "edges_scanned", "atomics",
                                       "pushes_dynamic"))):
         _, st_wg = _check(g, algo, "wg")
@@ -107,6 +110,8 @@ def test_paths_agree_on_schedule(offsets_dtype, monkeypatch):
         for k in keys:
             assert st_wg[k] == st_grid[k] == st_auto[k], (algo, k, st_wg[k], st_grid[k], st_auto[k])
         if algo == "peelone":
+            for st in (st_wg, st_grid, st_auto):
+                assert 0 < st["pushes_dynamic"] < st["frontier_total"]
             assert st_auto["scans"] == st_grid["scans"]
             assert st_wg["scans"] <= st_grid["scans"] <= st_wg["scans"] + 1
 
