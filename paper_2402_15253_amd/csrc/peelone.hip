@@ -414,15 +414,26 @@ __device__ void po_scan(const PoArgs<Off> &a, PoCtx<Off> &c, const int32_t *__re
             }
             if (cv == k || ((kMode == kStatic || kMode == kGpp) && v >= 0 && cv < k)) cand |= 1u << r;
         }
+        // a candidate's claim and its row bounds in one round trip
+        bool won[kScanR];
+        long long vre[kScanR];
 #pragma unroll
         for (int r = 0; r < kScanR; ++r) {
-            int v = vv[r];
-            vrs[r] = 0;
-            vd[r] = 0;
-            if ((cand >> r & 1u) && claim_vertex(c.out, v, k)) {
-                fr |= 1u << r;
+            const int v = vv[r];
+            won[r] = false;
+            vrs[r] = vre[r] = 0;
+            if (cand >> r & 1u) {
+                won[r] = claim_vertex(c.out, v, k);
                 vrs[r] = (long long)a.off[v];
-                vd[r] = (int)((long long)a.off[v + 1] - vrs[r]);
+                vre[r] = (long long)a.off[v + 1];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kScanR; ++r) {
+            vd[r] = 0;
+            if (won[r]) {
+                fr |= 1u << r;
+                vd[r] = (int)(vre[r] - vrs[r]);
                 dsum += vd[r];
             }
         }
