@@ -184,8 +184,9 @@ def random_access_roof(pico, st: dict, n: int, m: int, per_kernel: dict, ops: in
     """The persistent kernels' times against what their random accesses
     alone cost at the rates this GPU reaches (pico_probe_random_access) over
     arrays of the sizes they touch: the per-vertex value array (4n bytes)
-    and HistoCore's histogram (4m bytes).  PeelOne gathers one neighbour
-    value per adjacency entry and makes one atomic per decrement; HistoCore
+    and HistoCore's histogram (4m bytes).  PeelOne gathers at most one
+    neighbour value per adjacency entry (batches it expands locally skip the
+    read) and makes one atomic per decrement; HistoCore
     gathers one neighbour value per adjacency entry in InitHisto and in each
     round that rebuilds the histograms, and makes two atomics per histogram
     move (UpdateHisto's own value gathers, behind the neighbour-value bound,
