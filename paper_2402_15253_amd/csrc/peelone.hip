@@ -9,10 +9,11 @@
 //
 // Assertion decrement (Section III-B).  The paper's atomicSub_{>=k} stores
 // max(old - 1, k).  gfx950 has no clamped-decrement atomic, so the scatter
-// filters on core[u] > k (the test the paper puts before the atomic) and then
-// issues a plain fetch-and-subtract; the thread whose fetch returns exactly
-// k + 1 is the unique one that lowers u to k, so it alone asserts u into the
-// level's frontier and records out[u] = k.  A racing decrement that lands
+// filters on core[u] > k (the test the paper puts before the atomic; batches
+// expanded locally skip it, see "Local links") and then issues a plain
+// fetch-and-subtract; the thread whose fetch returns exactly k + 1 is the
+// unique one that lowers u to k, so it alone asserts u into the level's
+// frontier and records out[u] = k.  A racing decrement that lands
 // below k only touches a vertex already asserted at level k, whose final value
 // is held in `out`, and no vertex receives more than deg(u) decrements, so the
 // counter never underflows.  The vector produced is the one the clamped atomic
@@ -24,13 +25,13 @@
 // its own scan found while others still scan), so each vertex is claimed by
 // exactly one thread with a compare-and-swap of out[v] from -1 to k: the
 // scanner that reads core[v] == k, or the decrementer whose fetch returns
-// k + 1 (it lowered v to k) or k (a stale filter read let it lower a
-// not-yet-claimed level-k vertex below k).  Every vertex whose value reaches
-// k or less during level k meets one of these, so none is lost, and the
-// compare-and-swap lets only one expand it.  Once the level's scan phase
-// has ended (a grid barrier), every vertex valued k or less is claimed, so in
-// the level's rounds the one decrement whose fetch returns k + 1 claims its
-// vertex alone, with a plain store.
+// k + 1 (it lowered v to k) or k (an unfiltered local decrement, or a stale
+// filter read, lowered a not-yet-claimed level-k vertex below k).  Every
+// vertex whose value reaches k or less during level k meets one of these, so
+// none is lost, and the compare-and-swap lets only one expand it.  Once the
+// level's scan phase has ended (a grid barrier), every vertex valued k or
+// less is claimed, so in the level's rounds the one decrement whose fetch
+// returns k + 1 claims its vertex alone, with a plain store.
 //
 // Dynamic frontier (Section III-C, step 3).  An asserted vertex is processed
 // in the same level.  While the work it brings is small, the workgroup that

@@ -42,14 +42,27 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
 
 
-def source_hash(kernel: str) -> str:
-    """Hash of the HIP sources one kernel is built from."""
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
+def code_hash(sources) -> str:
+    """Hash of (file name, text) pairs with comments and whitespace removed, so
+    an edit of the comments alone keeps the hash while any change to the code
+    changes it."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
+    for name, text in sources:
+        h.update(name.encode())
+        h.update("".join(_COMMENT.sub(" ", text).split()).encode())
     return h.hexdigest()[:16]
+
+
+def source_hash(kernel: str) -> str:
+    """Hash of the HIP code one kernel is built from (see code_hash)."""
+    texts = []
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as f:
+            texts.append((name, f.read()))
+    return code_hash(texts)
 
 
 def _find(d: str, suffix: str) -> str:

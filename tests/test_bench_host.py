@@ -88,3 +88,14 @@ def test_autotune_key_names_kernel_revision(monkeypatch):
     key = at._key(batch, "peelone")
     assert key.startswith("gfx950|256|peelone|G4|n25|m2e+02|")
     assert key.endswith(source_hash("batched_kernel"))
+
+
+def test_code_hash_ignores_comments_not_code():
+    """A profile summary stays matched to its kernel through comment and layout
+    edits, and stops matching at any change to the code."""
+    from paper_2402_15253_amd.profiling import code_hash
+
+    base = code_hash([("k.hip", "int f(int x) { return x + 1; }  // add one\n")])
+    assert base == code_hash([("k.hip", "/* add\n   one */\nint f(int x)\n{\n    return x + 1;\n}\n")])
+    assert base != code_hash([("k.hip", "int f(int x) { return x + 2; }  // add one\n")])
+    assert base != code_hash([("j.hip", "int f(int x) { return x + 1; }")])
